@@ -1,0 +1,270 @@
+"""FP64 CPU oracle of the isotropic phase-field step (arXiv:2110.12448).
+
+TEST INFRASTRUCTURE ONLY.  The test suite, ``__graft_entry__.smoke()`` and the
+benchmark's ``cpu_baseline`` leg are the only callers.  The product library in
+``paper_2110_12448_amd`` never imports this package, and this package never
+imports the product.
+
+The arithmetic lives in ``pf_oracle.c`` (plain C, FP64, one function per
+discretised term of the paper).  This module only compiles it with gcc and
+marshals numpy arrays through ctypes.  Arrays are C-ordered ``(ny, nx)`` in 2D
+and ``(nz, ny, nx)`` in 3D, x fastest.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pf_oracle.c")
+_HDR = os.path.join(_HERE, "pf_oracle.h")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+NOFLUX = 0
+PERIODIC = 1
+
+
+def build(force: bool = True) -> str:
+    """Compile pf_oracle.c into liboracle.so with gcc (-O2, OpenMP, no fast-math)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= max(
+        os.path.getmtime(_SRC), os.path.getmtime(_HDR)
+    ):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
+           "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Params(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("w", C.c_double * 3),
+        ("k", C.c_double), ("eps4", C.c_double), ("D", C.c_double),
+        ("lam", C.c_double), ("h", C.c_double), ("dt", C.c_double),
+        ("Vp", C.c_double), ("lT", C.c_double), ("y0", C.c_double),
+        ("bc", C.c_int32 * 3), ("frame", C.c_int32), ("shift_row", C.c_int32),
+        ("n_grains", C.c_int32), ("rot", C.POINTER(C.c_double)),
+        ("round_f32", C.c_int32),
+    ]
+
+
+class _Tip(C.Structure):
+    _fields_ = [("found", C.c_int32), ("idx", C.c_int64),
+                ("x", C.c_double), ("y", C.c_double), ("z", C.c_double)]
+
+
+class _State(C.Structure):
+    _fields_ = [("step", C.c_int64), ("shift", C.c_int64), ("nonfinite", C.c_int64)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        lib = C.CDLL(_LIB)
+        dp = C.POINTER(C.c_double)
+        pp = C.POINTER(_Params)
+        i8 = C.POINTER(C.c_int8)
+        lib.or_phi.argtypes = [pp, dp, dp]
+        lib.or_laplacian.argtypes = [pp, dp, dp]
+        lib.or_grad_square.argtypes = [pp, dp, dp]
+        lib.or_divergence.argtypes = [pp, dp, dp, dp]
+        lib.or_anis_center.argtypes = [pp, dp, i8, dp]
+        lib.or_anis_remainder.argtypes = [pp, dp, i8, dp]
+        lib.or_rates.argtypes = [pp, dp, dp, i8, C.c_int64, C.c_int64, dp, dp]
+        lib.or_step.argtypes = [pp, dp, dp, i8, C.c_int64, C.POINTER(_State)]
+        lib.or_step.restype = C.c_int
+        lib.or_tip_find.argtypes = [pp, dp, C.POINTER(_Tip)]
+        lib.or_solid_fraction.argtypes = [pp, dp]
+        lib.or_solid_fraction.restype = C.c_double
+        lib.or_num_threads.restype = C.c_int
+        _lib = lib
+    return _lib
+
+
+@dataclass
+class Params:
+    """Problem description in the paper's dimensionless units (W, tau_0)."""
+    dim: int
+    nx: int
+    ny: int
+    nz: int = 1
+    w: Sequence[float] = (2.0 / 3.0, 1.0 / 3.0, 0.0)
+    k: float = 0.15
+    eps4: float = 0.02
+    D: float = 2.0
+    lam: float = 2.0 * 75.0 / 47.0
+    h: float = 0.8
+    dt: float = 0.064
+    Vp: float = 0.0
+    lT: float = 0.0
+    y0: float = 0.0
+    bc: Sequence[int] = (PERIODIC, NOFLUX, NOFLUX)
+    frame: int = 0
+    shift_row: int = 0
+    rot: Optional[np.ndarray] = None   # (n_grains, 3, 3) crystal -> lab
+    round_f32: int = 0
+    _keep: list = field(default_factory=list, repr=False)
+
+    @classmethod
+    def from_problem(cls, prob: dict, **over) -> "Params":
+        keys = {f for f in cls.__dataclass_fields__ if not f.startswith("_")}
+        kw = {k: v for k, v in prob.items() if k in keys}
+        kw.update(over)
+        return cls(**kw)
+
+    def shape(self):
+        return (self.nz, self.ny, self.nx) if self.dim == 3 else (self.ny, self.nx)
+
+    def _c(self) -> _Params:
+        rot = np.eye(3)[None] if self.rot is None else np.asarray(self.rot, dtype=np.float64)
+        rot = np.ascontiguousarray(rot.reshape(-1, 3, 3), dtype=np.float64)
+        self._keep = [rot]
+        cp = _Params()
+        cp.dim, cp.nx, cp.ny = self.dim, self.nx, self.ny
+        cp.nz = self.nz if self.dim == 3 else 1
+        for i in range(3):
+            cp.w[i] = float(self.w[i]) if i < len(self.w) else 0.0
+            cp.bc[i] = int(self.bc[i])
+        cp.k, cp.eps4, cp.D, cp.lam = self.k, self.eps4, self.D, self.lam
+        cp.h, cp.dt, cp.Vp, cp.lT, cp.y0 = self.h, self.dt, self.Vp, self.lT, self.y0
+        cp.frame, cp.shift_row = int(self.frame), int(self.shift_row)
+        cp.n_grains = rot.shape[0]
+        cp.rot = rot.ctypes.data_as(C.POINTER(C.c_double))
+        cp.round_f32 = int(self.round_f32)
+        return cp
+
+
+def _d(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(p: Params, a) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != p.shape():
+        raise ValueError("array shape %s does not match grid %s" % (a.shape, p.shape()))
+    return a
+
+
+def _grain(p: Params, g):
+    if g is None:
+        return None, None
+    g = np.ascontiguousarray(g, dtype=np.int8)
+    if g.shape != p.shape():
+        raise ValueError("grain shape mismatch")
+    return g, g.ctypes.data_as(C.POINTER(C.c_int8))
+
+
+def _unary(fn, p: Params, psi):
+    lib = _load()
+    psi = _f64(p, psi)
+    out = np.empty_like(psi)
+    cp = p._c()
+    getattr(lib, fn)(C.byref(cp), _d(psi), _d(out))
+    return out
+
+
+def phi(p: Params, psi):
+    return _unary("or_phi", p, psi)
+
+
+def laplacian(p: Params, psi):
+    return _unary("or_laplacian", p, psi)
+
+
+def grad_square(p: Params, psi):
+    return _unary("or_grad_square", p, psi)
+
+
+def divergence(p: Params, alpha, beta):
+    lib = _load()
+    a, b = _f64(p, alpha), _f64(p, beta)
+    out = np.empty_like(a)
+    cp = p._c()
+    lib.or_divergence(C.byref(cp), _d(a), _d(b), _d(out))
+    return out
+
+
+def anis_center(p: Params, psi, grain=None):
+    lib = _load()
+    psi = _f64(p, psi)
+    g, gp = _grain(p, grain)
+    out = np.empty_like(psi)
+    cp = p._c()
+    lib.or_anis_center(C.byref(cp), _d(psi), gp, _d(out))
+    return out
+
+
+def anis_remainder(p: Params, psi, grain=None):
+    lib = _load()
+    psi = _f64(p, psi)
+    g, gp = _grain(p, grain)
+    out = np.empty_like(psi)
+    cp = p._c()
+    lib.or_anis_remainder(C.byref(cp), _d(psi), gp, _d(out))
+    return out
+
+
+def rates(p: Params, psi, U, grain=None, n: int = 0, s: int = 0):
+    lib = _load()
+    psi, U = _f64(p, psi), _f64(p, U)
+    g, gp = _grain(p, grain)
+    rp, ru = np.empty_like(psi), np.empty_like(U)
+    cp = p._c()
+    lib.or_rates(C.byref(cp), _d(psi), _d(U), gp, int(n), int(s), _d(rp), _d(ru))
+    return rp, ru
+
+
+class State:
+    def __init__(self, step: int = 0, shift: int = 0):
+        self.step, self.shift, self.nonfinite = int(step), int(shift), 0
+
+    def __repr__(self):
+        return "State(step=%d, shift=%d, nonfinite=%d)" % (self.step, self.shift, self.nonfinite)
+
+
+def step(p: Params, psi, U, grain=None, nsteps: int = 1, state: Optional[State] = None):
+    """Advance nsteps; returns new (psi, U) arrays and the updated State."""
+    lib = _load()
+    psi = _f64(p, psi).copy()
+    U = _f64(p, U).copy()
+    g, gp = _grain(p, grain)
+    st = state if state is not None else State()
+    cs = _State(st.step, st.shift, 0)
+    cp = p._c()
+    rc = lib.or_step(C.byref(cp), _d(psi), _d(U), gp, int(nsteps), C.byref(cs))
+    if rc != 0:
+        raise MemoryError("oracle step failed")
+    st.step, st.shift, st.nonfinite = cs.step, cs.shift, cs.nonfinite
+    return psi, U, st
+
+
+def tip(p: Params, phi_field) -> dict:
+    lib = _load()
+    f = _f64(p, phi_field)
+    t = _Tip()
+    cp = p._c()
+    lib.or_tip_find(C.byref(cp), _d(f), C.byref(t))
+    return {"found": bool(t.found), "idx": int(t.idx), "x": t.x, "y": t.y, "z": t.z}
+
+
+def solid_fraction(p: Params, phi_field) -> float:
+    lib = _load()
+    f = _f64(p, phi_field)
+    cp = p._c()
+    return float(lib.or_solid_fraction(C.byref(cp), _d(f)))
+
+
+def num_threads() -> int:
+    return int(_load().or_num_threads())
