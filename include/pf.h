@@ -1,0 +1,166 @@
+/*
+ * pf.h -- C ABI of the MI355X phase-field library (libpfiso.so).
+ *
+ * One explicit time step of the quantitative phase-field model of dilute
+ * binary-alloy solidification with the O(h^2)-isotropic finite-difference
+ * operators of K. Ji, A. Molavi Tabrizi & A. Karma, "Isotropic
+ * finite-difference approximations for phase-field simulations of
+ * polycrystalline alloy solidification" (arXiv:2110.12448):
+ *   - the preconditioned phase field psi, phi = tanh(psi/sqrt2) (Sec. 2),
+ *     evolved by Eq. PF_a, and the supersaturation U evolved by Eq. PF_b with
+ *     the approximated anti-trapping current of Eq. Anti_approx (Sec. 2.3);
+ *   - Laplacian, gradient square and divergence mixed from lattice-shell
+ *     bases (Eqs. tau_2D, tau_3D; Sec. 3, Sec. 5, App. A): S-bar_{2,1} in 2D
+ *     and S-bar_{1,2,0} in 3D by default;
+ *   - cubic interface anisotropy rotated per grain (Eq. anis_function), its
+ *     eps4-linear terms on the standard <10>/<100> shell (Sec. 2.2, 4.3.1);
+ *   - frozen temperature (Eqs. Thermal_F1, Thermal_F2) or isothermal growth;
+ *   - explicit Euler in time (Sec. 4.3.1).
+ *
+ * Units: lengths in the interface width W, times in tau_0.  Lattice cell
+ * (i, j, l) sits at (i h, j h, l h); y (index j) is the growth and thermal
+ * axis.  Host arrays are row-major with x fastest: idx = i + nx*(j + ny*l).
+ *
+ * Errors: every int-returning call returns PF_OK (0) or a negative PF_ERR_*
+ * code and leaves out-parameters untouched on failure; pf_last_error()
+ * describes the last failure of the calling thread.  No exception crosses
+ * this interface.  Threading: a solver belongs to the stream it was created
+ * on; distinct solvers are independent and may run concurrently.
+ */
+#ifndef PF_H
+#define PF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PF_VERSION 1
+
+/* return codes */
+#define PF_OK 0
+#define PF_ERR_ARG (-1)          /* invalid argument or inconsistent parameters */
+#define PF_ERR_UNSTABLE_DT (-2)  /* dt above the explicit stability limit */
+#define PF_ERR_OOM (-3)          /* device allocation failed or workspace too small */
+#define PF_ERR_DEVICE (-4)       /* a HIP runtime call failed */
+#define PF_ERR_NONFINITE (-5)    /* the state holds NaN or Inf values */
+#define PF_ERR_STATE (-6)        /* call not valid in the solver's state */
+
+/* precision of the stored and stepped fields */
+#define PF_F32 0
+#define PF_F64 1
+
+/* boundary condition per axis (Sec. 4.3.2, 6.2.2) */
+#define PF_BC_NOFLUX 0           /* mirror about the boundary face */
+#define PF_BC_PERIODIC 1
+
+/* finite-difference scheme: shell weights of Eq. tau_2D / tau_3D applied to
+ * the Laplacian, the gradient square and both divergences */
+#define PF_SCHEME_ISO 0          /* 2D (2/3, 1/3); 3D (1/3, 2/3, 0) */
+#define PF_SCHEME_STD 1          /* 2D (1, 0);     3D (1, 0, 0) */
+#define PF_SCHEME_WEIGHTS 2      /* pf_params.weights, normalised to sum 1 */
+
+typedef struct pf_params {
+  int32_t dim;          /* 2 or 3 */
+  int32_t nx, ny, nz;   /* lattice size, each >= 4 (nz ignored in 2D) */
+  int32_t precision;    /* PF_F32 or PF_F64 */
+  int32_t scheme;       /* PF_SCHEME_* */
+  double weights[3];    /* shell weights for PF_SCHEME_WEIGHTS (3D: <100>,<110>,<111>) */
+  double k;             /* interface partition coefficient, 0 < k < 1 */
+  double eps4;          /* anisotropy strength, 0 <= eps4 < 1/15 */
+  double D;             /* dimensionless diffusivity D~ = D tau0 / W^2 > 0 */
+  double lambda;        /* coupling constant; <= 0 selects D~/a2, a2 = 47/75 (Sec. 2.1) */
+  double h;             /* lattice spacing in units of W (the paper's h/W) */
+  double dt;            /* time step in tau0; <= 0 selects 0.8 x pf_stable_dt() */
+  double Vp;            /* pulling speed V~p (frozen temperature) */
+  double lT;            /* thermal length l~T; <= 0 selects the isothermal limit */
+  double y0;            /* isotherm origin: zeta = y + s h - y0 - Vp t */
+  int32_t bc[3];        /* PF_BC_* for x, y, z */
+  int32_t frame;        /* 1: moving frame along +y (requires bc[1] == PF_BC_NOFLUX) */
+  int32_t shift_row;    /* frame moves one row when y_tip >= shift_row * h; 1..ny-2 */
+  int32_t n_grains;     /* 1..127 */
+  const double *grain_rot; /* n_grains x 9, row-major proper rotations, crystal -> lab */
+} pf_params;
+
+typedef struct pf_init {
+  const double *psi;    /* nx*ny*nz initial psi (host, FP64, finite) */
+  const double *U;      /* nx*ny*nz initial U (host, FP64, finite) */
+  const int8_t *grain;  /* nx*ny*nz grain index in [0, n_grains), or NULL for all 0;
+                           with the frame on it must not vary along y */
+} pf_init;
+
+typedef struct pf_tip {
+  int64_t step;          /* steps taken */
+  double t;              /* step * dt */
+  int32_t found;         /* 0 when no cell pair crosses phi = 0 along y */
+  int32_t nonfinite;     /* 1 when any psi or U value is NaN or Inf */
+  int64_t index;         /* linear frame index of the cell below the crossing */
+  double x, y_frame, z;  /* tip position in the frame (W) */
+  double y_lab;          /* y_frame + frame_shift * h, in FP64 */
+  double velocity;       /* d y_lab / dt between the last two pf_tip_state calls (0 at first) */
+  double solid_fraction; /* (1/N) sum (1 + phi)/2, FP64 */
+  int64_t frame_shift;   /* rows the frame has moved */
+} pf_tip;
+
+typedef struct pf_solver pf_solver;
+
+/* Library version (PF_VERSION). */
+int pf_version(void);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char *pf_last_error(void);
+
+/* Explicit stability limit used by pf_create: h^2 / (2 dim max(D~, 1/F1_min))
+ * with F1_min the smallest F1 of Eq. Thermal_F1 over the initial lattice
+ * (1 when isothermal), the paper's rule of Sec. 4.3.1 / 6.2.1 with the
+ * psi-equation diffusivity included.  Returns a negative value on bad input. */
+double pf_stable_dt(const pf_params *p);
+
+/* Device bytes pf_create needs when the caller provides the memory. */
+size_t pf_workspace_bytes(const pf_params *p);
+
+/* Create a solver on `stream` (a hipStream_t; NULL for the null stream) of
+ * the current device.  Copies p, p->grain_rot and the init arrays; the caller
+ * keeps ownership of every host pointer.  If `workspace` is non-NULL it is
+ * caller-owned device memory of at least pf_workspace_bytes(p) bytes, 256-byte
+ * aligned, that must outlive the solver; otherwise the library allocates and
+ * pf_destroy frees.  Validates the parameters (PF_ERR_ARG), dt against
+ * pf_stable_dt (PF_ERR_UNSTABLE_DT) and the init arrays (PF_ERR_NONFINITE). */
+int pf_create(const pf_params *p, const pf_init *init, void *workspace,
+              size_t workspace_bytes, void *stream, pf_solver **out);
+
+/* Enqueue nsteps (>= 0) time steps on the solver's stream; returns without
+ * waiting.  Non-finite values surface at the next pf_tip_state. */
+int pf_step(pf_solver *s, int64_t nsteps);
+
+/* Wait for the solver's stream. */
+int pf_synchronize(pf_solver *s);
+
+/* Synchronise and copy the state to host FP64 arrays of nx*ny*nz values in
+ * frame coordinates: phi = tanh(psi/sqrt2), U, psi.  Any pointer may be NULL.
+ * grain (int8) likewise. */
+int pf_read_fields(pf_solver *s, double *phi, double *U, double *psi, int8_t *grain);
+
+/* Synchronise, reduce the current state on the device (tip of phi, solid
+ * fraction, non-finite check; FP64 accumulation) and fill *out.  Returns
+ * PF_ERR_NONFINITE (with *out filled) when the state holds NaN or Inf. */
+int pf_tip_state(pf_solver *s, pf_tip *out);
+
+/* Device pointers of the current psi and U arrays (element type per
+ * precision, nx*ny*nz each, frame rows possibly pending one shift: see
+ * pf_frame_state).  Valid until the next pf_step. */
+int pf_device_fields(pf_solver *s, void **psi, void **U);
+
+/* Rows moved so far and whether the current device arrays still owe one
+ * downward shift (applied on the fly by the next step and by the readers). */
+int pf_frame_state(pf_solver *s, int64_t *shift, int32_t *pending);
+
+/* Release the solver (and its workspace if the library allocated it). */
+void pf_destroy(pf_solver *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

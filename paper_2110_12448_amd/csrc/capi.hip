@@ -1,0 +1,563 @@
+// capi.hip -- the C ABI of include/pf.h: parameter validation, workspace
+// layout, state upload/download and the per-step launch sequence.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pf_device.hpp"
+#include "pf_internal.hpp"
+
+using namespace pf;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define PF_HIP(call)                                                          \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess)                                                     \
+      return fail(PF_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// thin-interface constant a2 = 47/75 (Sec. 2.1): default lambda = D~ / a2
+constexpr double kA2 = 47.0 / 75.0;
+constexpr int kDefaultSeg2D = 16;
+constexpr int kDefaultSeg3D = 16;
+constexpr int kDefaultZTile3D = 4;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t cells(const pf_params *p) {
+  return (size_t)p->nx * (size_t)p->ny * (size_t)(p->dim == 3 ? p->nz : 1);
+}
+
+void weights_of(const pf_params *p, double w[3]) {
+  if (p->scheme == PF_SCHEME_STD) {
+    w[0] = 1.0; w[1] = 0.0; w[2] = 0.0;
+  } else if (p->scheme == PF_SCHEME_WEIGHTS) {
+    double s = p->weights[0] + p->weights[1] + (p->dim == 3 ? p->weights[2] : 0.0);
+    w[0] = p->weights[0] / s;
+    w[1] = p->weights[1] / s;
+    w[2] = p->dim == 3 ? p->weights[2] / s : 0.0;
+  } else if (p->dim == 2) {
+    w[0] = 2.0 / 3.0; w[1] = 1.0 / 3.0; w[2] = 0.0;
+  } else {
+    w[0] = 1.0 / 3.0; w[1] = 2.0 / 3.0; w[2] = 0.0;
+  }
+}
+
+// smallest F1 of Eq. Thermal_F1 over the lattice at t = 0 (1 if isothermal)
+double f1_min(const pf_params *p) {
+  if (!(p->lT > 0.0)) return 1.0;
+  double zmax = (p->ny - 1) * p->h - p->y0;
+  double zmin = -p->y0;
+  double a = 1.0 - (1.0 - p->k) * zmax / p->lT;
+  double b = 1.0 - (1.0 - p->k) * zmin / p->lT;
+  return a < b ? a : b;
+}
+
+int max_step_blocks(const pf_params *p, int seg, int ztile) {
+  if (p->dim == 2) return geom2d(p->nx, p->ny, seg).blocks;
+  return geom3d(p->nx, p->ny, p->nz, seg, ztile).blocks;
+}
+
+struct Layout {
+  size_t psi[2], U[2], grain, rot, frame[2], partials, counter, result, total;
+};
+
+Layout layout_of(const pf_params *p) {
+  Layout L;
+  size_t es = p->precision == PF_F64 ? 8 : 4;
+  size_t n = cells(p);
+  size_t o = 0;
+  for (int i = 0; i < 2; ++i) { L.psi[i] = o; o += align256(n * es); }
+  for (int i = 0; i < 2; ++i) { L.U[i] = o; o += align256(n * es); }
+  L.grain = o; o += align256(p->n_grains > 1 ? n : 1);
+  L.rot = o; o += align256((size_t)(p->n_grains > 0 ? p->n_grains : 1) * 9 * es);
+  for (int i = 0; i < 2; ++i) { L.frame[i] = o; o += 256; }
+  // per-block partials: enough for the finest segmentation the step accepts
+  int nb = std::max(max_step_blocks(p, 4, 1), reduce_blocks(p->nx, p->ny, p->dim == 3 ? p->nz : 1));
+  L.partials = o; o += align256((size_t)(nb + 64) * tip_acc_bytes());
+  L.counter = o; o += 256;
+  L.result = o; o += 256;
+  L.total = o;
+  return L;
+}
+
+int validate(const pf_params *p) {
+  if (!p) return fail(PF_ERR_ARG, "params is NULL");
+  if (p->dim != 2 && p->dim != 3) return fail(PF_ERR_ARG, "dim must be 2 or 3");
+  if (p->nx < 4 || p->ny < 4 || (p->dim == 3 && p->nz < 4))
+    return fail(PF_ERR_ARG, "every lattice side must be >= 4");
+  if ((double)p->nx * p->ny * (p->dim == 3 ? p->nz : 1) > 4.0e9)
+    return fail(PF_ERR_ARG, "lattice larger than 4e9 cells");
+  if ((long long)p->nx * p->ny > 2147483647LL / 2)
+    return fail(PF_ERR_ARG, "x-y plane too large");
+  if (p->precision != PF_F32 && p->precision != PF_F64)
+    return fail(PF_ERR_ARG, "precision must be PF_F32 or PF_F64");
+  if (p->scheme < PF_SCHEME_ISO || p->scheme > PF_SCHEME_WEIGHTS)
+    return fail(PF_ERR_ARG, "unknown scheme");
+  if (p->scheme == PF_SCHEME_WEIGHTS) {
+    double s = p->weights[0] + p->weights[1] + (p->dim == 3 ? p->weights[2] : 0.0);
+    if (!(fabs(s) > 1e-12)) return fail(PF_ERR_ARG, "shell weights sum to zero");
+    if (p->dim == 2 && p->weights[2] != 0.0)
+      return fail(PF_ERR_ARG, "2D has two shells: weights[2] must be 0");
+  }
+  if (!(p->k > 0.0 && p->k < 1.0)) return fail(PF_ERR_ARG, "k must lie in (0, 1)");
+  if (!(p->eps4 >= 0.0 && p->eps4 < 1.0 / 15.0))
+    return fail(PF_ERR_ARG, "eps4 must lie in [0, 1/15)");
+  if (!(p->D > 0.0)) return fail(PF_ERR_ARG, "D must be > 0");
+  if (!(p->h > 0.0)) return fail(PF_ERR_ARG, "h must be > 0");
+  if (!isfinite(p->lambda) || !isfinite(p->dt) || !isfinite(p->Vp) || !isfinite(p->lT) ||
+      !isfinite(p->y0))
+    return fail(PF_ERR_ARG, "non-finite scalar parameter");
+  for (int a = 0; a < 3; ++a)
+    if (p->bc[a] != PF_BC_NOFLUX && p->bc[a] != PF_BC_PERIODIC)
+      return fail(PF_ERR_ARG, "bc must be PF_BC_NOFLUX or PF_BC_PERIODIC");
+  if (p->frame) {
+    if (p->bc[1] != PF_BC_NOFLUX) return fail(PF_ERR_ARG, "the moving frame needs no-flux y walls");
+    if (p->shift_row < 1 || p->shift_row > p->ny - 2)
+      return fail(PF_ERR_ARG, "shift_row must lie in [1, ny-2]");
+  }
+  if (p->n_grains < 1 || p->n_grains > 127) return fail(PF_ERR_ARG, "n_grains must be 1..127");
+  if (!p->grain_rot) return fail(PF_ERR_ARG, "grain_rot is NULL");
+  for (int g = 0; g < p->n_grains; ++g) {
+    const double *R = p->grain_rot + 9 * g;
+    for (int i = 0; i < 9; ++i)
+      if (!isfinite(R[i])) return fail(PF_ERR_ARG, "non-finite rotation entry");
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double d = 0.0;
+        for (int m = 0; m < 3; ++m) d += R[m * 3 + i] * R[m * 3 + j];
+        if (fabs(d - (i == j ? 1.0 : 0.0)) > 1e-9)
+          return fail(PF_ERR_ARG, "grain rotation is not orthonormal");
+      }
+    double det = R[0] * (R[4] * R[8] - R[5] * R[7]) - R[1] * (R[3] * R[8] - R[5] * R[6]) +
+                 R[2] * (R[3] * R[7] - R[4] * R[6]);
+    if (det < 0.0) return fail(PF_ERR_ARG, "grain rotation is improper (det < 0)");
+    if (p->dim == 2 && (fabs(R[2]) > 1e-12 || fabs(R[5]) > 1e-12 || fabs(R[6]) > 1e-12 ||
+                        fabs(R[7]) > 1e-12))
+      return fail(PF_ERR_ARG, "2D grain rotations must be rotations about z");
+  }
+  if (p->lT > 0.0 && !(f1_min(p) > 0.0))
+    return fail(PF_ERR_ARG, "F1 = 1 - (1-k) zeta / lT is not positive over the lattice");
+  return PF_OK;
+}
+
+}  // namespace
+
+struct pf_solver {
+  pf_params p;
+  std::vector<double> rot;
+  double w[3];
+  double lambda, dt;
+  size_t n;
+  hipStream_t stream;
+  char *ws;
+  size_t ws_bytes;
+  bool own;
+  Layout L;
+  int cur;    // current field buffers
+  int fcur;   // current frame record
+  long long step;
+  int seg, ztile;
+  bool have_prev;
+  double prev_t, prev_y;
+};
+
+namespace {
+
+template <typename T>
+T *field(pf_solver *s, size_t off) {
+  return reinterpret_cast<T *>(s->ws + off);
+}
+
+template <typename T>
+Coef<T> coef_of(const pf_solver *s) {
+  const pf_params &p = s->p;
+  const double h = p.h, h2 = h * h;
+  Coef<T> c;
+  c.dt = (T)s->dt;
+  c.k = (T)p.k;
+  c.omk = (T)(1.0 - p.k);
+  c.eps4 = (T)p.eps4;
+  c.D = (T)p.D;
+  c.lambda = (T)s->lambda;
+  c.inv_h = (T)(1.0 / h);
+  c.h = (T)h;
+  c.cStd = (T)(1.0 / h2);
+  c.inv_lT = (T)(p.lT > 0.0 ? 1.0 / p.lT : 0.0);
+  if (p.dim == 2) {
+    // L_{1,0} = s10/h^2, L_{0,1} = s11/(2h^2) (Eqs. 2D_L10, 2D_L01)
+    c.cL1 = (T)(s->w[0] / h2);
+    c.cL2 = (T)(s->w[1] / (2.0 * h2));
+    c.cL3 = (T)0;
+    // G_{1,0} = (...)/(4h^2), G_{0,1} = (...)/(8h^2) (Eqs. Grad_10, Grad_11)
+    c.cG1 = (T)(s->w[0] / (4.0 * h2));
+    c.cG2 = (T)(s->w[1] / (8.0 * h2));
+    c.cG3 = (T)0;
+    // D_{1,0}: fluxes carry the 4-point alpha sum, /(4h^2); D_{0,1}: plaquette
+    // means times dbeta, /(2h^2) (Eqs. flux_10, flux_11)
+    c.cD1 = (T)(s->w[0] / (4.0 * h2));
+    c.cD2 = (T)(s->w[1] / (2.0 * h2));
+    c.cD3 = (T)0;
+  } else {
+    // L_{1,0,0} = s/h^2, L_{0,1,0} = s/(4h^2), L_{0,0,1} = s/(4h^2)
+    c.cL1 = (T)(s->w[0] / h2);
+    c.cL2 = (T)(s->w[1] / (4.0 * h2));
+    c.cL3 = (T)(s->w[2] / (4.0 * h2));
+    // G_{1,0,0} = /(4h^2), G_{0,1,0} = /(16h^2), G_{0,0,1} = /(16h^2)
+    c.cG1 = (T)(s->w[0] / (4.0 * h2));
+    c.cG2 = (T)(s->w[1] / (16.0 * h2));
+    c.cG3 = (T)(s->w[2] / (16.0 * h2));
+    // D_{1,0,0} = sum abar dbeta / h^2; D_{0,1,0}, D_{0,0,1} = / (4h^2)
+    c.cD1 = (T)(s->w[0] / h2);
+    c.cD2 = (T)(s->w[1] / (4.0 * h2));
+    c.cD3 = (T)(s->w[2] / (4.0 * h2));
+  }
+  return c;
+}
+
+template <typename T>
+int upload(pf_solver *s, const pf_init *init) {
+  const size_t n = s->n;
+  std::vector<T> tmp(n);
+  for (size_t i = 0; i < n; ++i) tmp[i] = (T)init->psi[i];
+  PF_HIP(hipMemcpy(field<T>(s, s->L.psi[0]), tmp.data(), n * sizeof(T), hipMemcpyHostToDevice));
+  for (size_t i = 0; i < n; ++i) tmp[i] = (T)init->U[i];
+  PF_HIP(hipMemcpy(field<T>(s, s->L.U[0]), tmp.data(), n * sizeof(T), hipMemcpyHostToDevice));
+  // rotation table: 2D (r00, r01, r10, r11) per grain, 3D all 9
+  const int ng = s->p.n_grains;
+  std::vector<T> rt((size_t)ng * 9, (T)0);
+  for (int g = 0; g < ng; ++g) {
+    const double *R = s->rot.data() + 9 * g;
+    if (s->p.dim == 2) {
+      rt[4 * g + 0] = (T)R[0];
+      rt[4 * g + 1] = (T)R[1];
+      rt[4 * g + 2] = (T)R[3];
+      rt[4 * g + 3] = (T)R[4];
+    } else {
+      for (int i = 0; i < 9; ++i) rt[9 * g + i] = (T)R[i];
+    }
+  }
+  PF_HIP(hipMemcpy(s->ws + s->L.rot, rt.data(), rt.size() * sizeof(T), hipMemcpyHostToDevice));
+  return PF_OK;
+}
+
+template <typename T>
+int step_impl(pf_solver *s, long long nsteps) {
+  const pf_params &p = s->p;
+  const bool frozen = p.lT > 0.0;
+  const bool reduce = p.frame != 0;
+  const bool multi = p.n_grains > 1;
+  Reduce red{reinterpret_cast<TipAcc *>(s->ws + s->L.partials),
+             reinterpret_cast<unsigned *>(s->ws + s->L.counter),
+             reinterpret_cast<TipResult *>(s->ws + s->L.result)};
+  const Coef<T> c = coef_of<T>(s);
+  if (p.dim == 2) {
+    Step2DArgs<T> a;
+    memset(&a, 0, sizeof(a));
+    Geom2D g = geom2d(p.nx, p.ny, s->seg);
+    a.grain = multi ? reinterpret_cast<const int8_t *>(s->ws + s->L.grain) : nullptr;
+    a.rot = field<T>(s, s->L.rot);
+    a.r00 = (T)s->rot[0]; a.r01 = (T)s->rot[1]; a.r10 = (T)s->rot[3]; a.r11 = (T)s->rot[4];
+    a.nx = p.nx; a.ny = p.ny; a.bcx = p.bc[0]; a.bcy = p.bc[1];
+    a.wout = g.wout; a.nstrips = g.nstrips; a.nsegs = g.nsegs; a.seg = g.seg;
+    a.c = c;
+    a.hd = p.h; a.y0 = p.y0; a.Vp = p.Vp; a.dtd = s->dt;
+    a.frame = p.frame; a.shift_row = p.shift_row;
+    a.red = red;
+    for (long long i = 0; i < nsteps; ++i) {
+      a.psi_in = field<T>(s, s->L.psi[s->cur]);
+      a.U_in = field<T>(s, s->L.U[s->cur]);
+      a.psi_out = field<T>(s, s->L.psi[1 - s->cur]);
+      a.U_out = field<T>(s, s->L.U[1 - s->cur]);
+      a.frame_in = reinterpret_cast<const FrameState *>(s->ws + s->L.frame[s->fcur]);
+      a.frame_out = reinterpret_cast<FrameState *>(s->ws + s->L.frame[reduce ? 1 - s->fcur : s->fcur]);
+      a.step = s->step;
+      PF_HIP(launch_step2d<T>(a, g, frozen, reduce, multi, s->stream));
+      s->cur = 1 - s->cur;
+      if (reduce) s->fcur = 1 - s->fcur;
+      s->step += 1;
+    }
+  } else {
+    Step3DArgs<T> a;
+    memset(&a, 0, sizeof(a));
+    Geom3D g = geom3d(p.nx, p.ny, p.nz, s->seg, s->ztile);
+    a.grain = multi ? reinterpret_cast<const int8_t *>(s->ws + s->L.grain) : nullptr;
+    a.rot = field<T>(s, s->L.rot);
+    for (int i = 0; i < 9; ++i) a.R[i] = (T)s->rot[i];
+    a.nx = p.nx; a.ny = p.ny; a.nz = p.nz;
+    a.bcx = p.bc[0]; a.bcy = p.bc[1]; a.bcz = p.bc[2];
+    a.wout = g.wout; a.nstrips = g.nstrips; a.nzt = g.nzt; a.nsegs = g.nsegs; a.seg = g.seg;
+    a.ztile = g.ztile;
+    a.c = c;
+    a.hd = p.h; a.y0 = p.y0; a.Vp = p.Vp; a.dtd = s->dt;
+    a.frame = p.frame; a.shift_row = p.shift_row;
+    a.red = red;
+    for (long long i = 0; i < nsteps; ++i) {
+      a.psi_in = field<T>(s, s->L.psi[s->cur]);
+      a.U_in = field<T>(s, s->L.U[s->cur]);
+      a.psi_out = field<T>(s, s->L.psi[1 - s->cur]);
+      a.U_out = field<T>(s, s->L.U[1 - s->cur]);
+      a.frame_in = reinterpret_cast<const FrameState *>(s->ws + s->L.frame[s->fcur]);
+      a.frame_out = reinterpret_cast<FrameState *>(s->ws + s->L.frame[reduce ? 1 - s->fcur : s->fcur]);
+      a.step = s->step;
+      PF_HIP(launch_step3d<T>(a, g, frozen, reduce, multi, s->stream));
+      s->cur = 1 - s->cur;
+      if (reduce) s->fcur = 1 - s->fcur;
+      s->step += 1;
+    }
+  }
+  return PF_OK;
+}
+
+template <typename T>
+int reduce_impl(pf_solver *s, TipResult *res, FrameState *fr) {
+  ReduceArgs<T> a;
+  a.psi = field<T>(s, s->L.psi[s->cur]);
+  a.U = field<T>(s, s->L.U[s->cur]);
+  a.nx = s->p.nx; a.ny = s->p.ny; a.nz = s->p.dim == 3 ? s->p.nz : 1;
+  a.hd = s->p.h;
+  a.frame = reinterpret_cast<const FrameState *>(s->ws + s->L.frame[s->fcur]);
+  a.red = Reduce{reinterpret_cast<TipAcc *>(s->ws + s->L.partials),
+                 reinterpret_cast<unsigned *>(s->ws + s->L.counter),
+                 reinterpret_cast<TipResult *>(s->ws + s->L.result)};
+  PF_HIP(launch_reduce<T>(a, s->stream));
+  PF_HIP(hipMemcpyAsync(res, a.red.result, sizeof(TipResult), hipMemcpyDeviceToHost, s->stream));
+  PF_HIP(hipMemcpyAsync(fr, s->ws + s->L.frame[s->fcur], sizeof(FrameState), hipMemcpyDeviceToHost,
+                        s->stream));
+  PF_HIP(hipStreamSynchronize(s->stream));
+  return PF_OK;
+}
+
+template <typename T>
+int read_impl(pf_solver *s, double *phi, double *U, double *psi) {
+  const pf_params &p = s->p;
+  const size_t n = s->n;
+  FrameState fr;
+  PF_HIP(hipStreamSynchronize(s->stream));
+  PF_HIP(hipMemcpy(&fr, s->ws + s->L.frame[s->fcur], sizeof(fr), hipMemcpyDeviceToHost));
+  std::vector<T> hp(n), hu(n);
+  PF_HIP(hipMemcpy(hp.data(), field<T>(s, s->L.psi[s->cur]), n * sizeof(T), hipMemcpyDeviceToHost));
+  PF_HIP(hipMemcpy(hu.data(), field<T>(s, s->L.U[s->cur]), n * sizeof(T), hipMemcpyDeviceToHost));
+  const int nx = p.nx, ny = p.ny, nz = p.dim == 3 ? p.nz : 1;
+  for (int l = 0; l < nz; ++l)
+    for (int j = 0; j < ny; ++j) {
+      int jp = fr.pending ? std::min(j + 1, ny - 1) : j;
+      size_t dst = ((size_t)l * ny + j) * nx, src = ((size_t)l * ny + jp) * nx;
+      for (int i = 0; i < nx; ++i) {
+        double vp = (double)hp[src + i];
+        if (psi) psi[dst + i] = vp;
+        if (phi) phi[dst + i] = tanh(vp / sqrt(2.0));
+        if (U) U[dst + i] = (double)hu[src + i];
+      }
+    }
+  return PF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pf_version(void) { return PF_VERSION; }
+
+const char *pf_last_error(void) { return g_err.c_str(); }
+
+double pf_stable_dt(const pf_params *p) {
+  if (validate(p) != PF_OK) return -1.0;
+  double f1 = f1_min(p);
+  double diff = std::max(p->D, 1.0 / f1);
+  return p->h * p->h / (2.0 * p->dim * diff);
+}
+
+size_t pf_workspace_bytes(const pf_params *p) {
+  if (validate(p) != PF_OK) return 0;
+  return layout_of(p).total;
+}
+
+int pf_create(const pf_params *p, const pf_init *init, void *workspace, size_t workspace_bytes,
+              void *stream, pf_solver **out) {
+  int rc = validate(p);
+  if (rc != PF_OK) return rc;
+  if (!init || !init->psi || !init->U) return fail(PF_ERR_ARG, "init arrays are NULL");
+  if (!out) return fail(PF_ERR_ARG, "out is NULL");
+  const size_t n = cells(p);
+  for (size_t i = 0; i < n; ++i)
+    if (!isfinite(init->psi[i]) || !isfinite(init->U[i]))
+      return fail(PF_ERR_NONFINITE, "initial psi or U holds NaN or Inf");
+  if (init->grain) {
+    for (size_t i = 0; i < n; ++i)
+      if (init->grain[i] < 0 || init->grain[i] >= p->n_grains)
+        return fail(PF_ERR_ARG, "grain index outside [0, n_grains)");
+    if (p->frame) {
+      const int nx = p->nx, ny = p->ny, nz = p->dim == 3 ? p->nz : 1;
+      for (int l = 0; l < nz; ++l)
+        for (int j = 1; j < ny; ++j)
+          for (int i = 0; i < nx; ++i)
+            if (init->grain[((size_t)l * ny + j) * nx + i] != init->grain[(size_t)l * ny * nx + i])
+              return fail(PF_ERR_ARG, "with the moving frame the grain map must not vary along y");
+    }
+  }
+  double lambda = p->lambda > 0.0 ? p->lambda : p->D / kA2;
+  double dtmax = pf_stable_dt(p);
+  double dt = p->dt > 0.0 ? p->dt : 0.8 * dtmax;
+  if (dt > dtmax * (1.0 + 1e-12))
+    return fail(PF_ERR_UNSTABLE_DT, "dt = " + std::to_string(dt) + " exceeds the stability limit " +
+                                        std::to_string(dtmax));
+  Layout L = layout_of(p);
+  pf_solver *s = new (std::nothrow) pf_solver();
+  if (!s) return fail(PF_ERR_OOM, "host allocation failed");
+  s->p = *p;
+  s->rot.assign(p->grain_rot, p->grain_rot + 9 * p->n_grains);
+  s->p.grain_rot = s->rot.data();
+  weights_of(p, s->w);
+  s->lambda = lambda;
+  s->dt = dt;
+  s->n = n;
+  s->stream = reinterpret_cast<hipStream_t>(stream);
+  s->L = L;
+  s->cur = 0;
+  s->fcur = 0;
+  s->step = 0;
+  s->seg = p->dim == 2 ? kDefaultSeg2D : kDefaultSeg3D;
+  s->ztile = kDefaultZTile3D;
+  s->have_prev = false;
+  if (workspace) {
+    if (workspace_bytes < L.total || (reinterpret_cast<uintptr_t>(workspace) & 255u)) {
+      delete s;
+      return fail(PF_ERR_OOM, "workspace smaller than pf_workspace_bytes() or not 256-byte aligned");
+    }
+    s->ws = reinterpret_cast<char *>(workspace);
+    s->ws_bytes = workspace_bytes;
+    s->own = false;
+  } else {
+    void *d = nullptr;
+    if (hipMalloc(&d, L.total) != hipSuccess) {
+      delete s;
+      return fail(PF_ERR_OOM, "hipMalloc of " + std::to_string(L.total) + " bytes failed");
+    }
+    s->ws = reinterpret_cast<char *>(d);
+    s->ws_bytes = L.total;
+    s->own = true;
+  }
+  int r2 = p->precision == PF_F64 ? upload<double>(s, init) : upload<float>(s, init);
+  if (r2 == PF_OK && p->n_grains > 1) {
+    std::vector<int8_t> g(n, 0);
+    if (init->grain) memcpy(g.data(), init->grain, n);
+    if (hipMemcpy(s->ws + L.grain, g.data(), n, hipMemcpyHostToDevice) != hipSuccess)
+      r2 = fail(PF_ERR_DEVICE, "grain upload failed");
+  }
+  if (r2 == PF_OK) {
+    FrameState z{0, 0, 0};
+    if (hipMemcpy(s->ws + L.frame[0], &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(s->ws + L.frame[1], &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(s->ws + L.counter, 0, 256) != hipSuccess)
+      r2 = fail(PF_ERR_DEVICE, "state initialisation failed");
+  }
+  if (r2 != PF_OK) {
+    if (s->own) (void)hipFree(s->ws);
+    delete s;
+    return r2;
+  }
+  *out = s;
+  return PF_OK;
+}
+
+int pf_step(pf_solver *s, int64_t nsteps) {
+  if (!s) return fail(PF_ERR_ARG, "solver is NULL");
+  if (nsteps < 0) return fail(PF_ERR_ARG, "nsteps must be >= 0");
+  return s->p.precision == PF_F64 ? step_impl<double>(s, nsteps) : step_impl<float>(s, nsteps);
+}
+
+int pf_synchronize(pf_solver *s) {
+  if (!s) return fail(PF_ERR_ARG, "solver is NULL");
+  PF_HIP(hipStreamSynchronize(s->stream));
+  return PF_OK;
+}
+
+int pf_read_fields(pf_solver *s, double *phi, double *U, double *psi, int8_t *grain) {
+  if (!s) return fail(PF_ERR_ARG, "solver is NULL");
+  int rc = s->p.precision == PF_F64 ? read_impl<double>(s, phi, U, psi)
+                                    : read_impl<float>(s, phi, U, psi);
+  if (rc != PF_OK) return rc;
+  if (grain) {
+    if (s->p.n_grains > 1) {
+      PF_HIP(hipMemcpy(grain, s->ws + s->L.grain, s->n, hipMemcpyDeviceToHost));
+    } else {
+      memset(grain, 0, s->n);
+    }
+  }
+  return PF_OK;
+}
+
+int pf_tip_state(pf_solver *s, pf_tip *out) {
+  if (!s || !out) return fail(PF_ERR_ARG, "solver or out is NULL");
+  TipResult r;
+  FrameState fr;
+  int rc = s->p.precision == PF_F64 ? reduce_impl<double>(s, &r, &fr)
+                                    : reduce_impl<float>(s, &r, &fr);
+  if (rc != PF_OK) return rc;
+  const pf_params &p = s->p;
+  pf_tip t;
+  memset(&t, 0, sizeof(t));
+  t.step = s->step;
+  t.t = (double)s->step * s->dt;
+  t.found = r.found;
+  t.nonfinite = r.bad ? 1 : 0;
+  t.frame_shift = fr.shift;
+  t.solid_fraction = r.fs_sum / (double)s->n;
+  if (r.found) {
+    const long long nx = p.nx, ny = p.ny;
+    t.index = r.idx;
+    t.x = (double)(r.idx % nx) * p.h;
+    t.z = p.dim == 3 ? (double)(r.idx / (nx * ny)) * p.h : 0.0;
+    t.y_frame = r.y;
+    t.y_lab = r.y + (double)fr.shift * p.h;
+    if (s->have_prev && t.t > s->prev_t) t.velocity = (t.y_lab - s->prev_y) / (t.t - s->prev_t);
+    s->have_prev = true;
+    s->prev_t = t.t;
+    s->prev_y = t.y_lab;
+  } else {
+    t.index = -1;
+  }
+  *out = t;
+  if (r.bad) return fail(PF_ERR_NONFINITE, "state holds NaN or Inf values");
+  return PF_OK;
+}
+
+int pf_device_fields(pf_solver *s, void **psi, void **U) {
+  if (!s) return fail(PF_ERR_ARG, "solver is NULL");
+  if (psi) *psi = s->ws + s->L.psi[s->cur];
+  if (U) *U = s->ws + s->L.U[s->cur];
+  return PF_OK;
+}
+
+int pf_frame_state(pf_solver *s, int64_t *shift, int32_t *pending) {
+  if (!s) return fail(PF_ERR_ARG, "solver is NULL");
+  FrameState fr;
+  PF_HIP(hipStreamSynchronize(s->stream));
+  PF_HIP(hipMemcpy(&fr, s->ws + s->L.frame[s->fcur], sizeof(fr), hipMemcpyDeviceToHost));
+  if (shift) *shift = fr.shift;
+  if (pending) *pending = fr.pending;
+  return PF_OK;
+}
+
+void pf_destroy(pf_solver *s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->stream);
+  if (s->own) (void)hipFree(s->ws);
+  delete s;
+}
+
+}  // extern "C"

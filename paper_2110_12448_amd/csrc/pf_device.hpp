@@ -1,0 +1,172 @@
+// pf_device.hpp -- device-side building blocks shared by the gfx950 step and
+// reduction kernels: per-precision math, wave64 cross-lane moves, boundary
+// ghost maps and the FP64 tip / solid-fraction record.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pf_internal.hpp"
+
+namespace pf {
+
+// ------------------------------------------------------------------ math
+
+template <typename T> struct Math;
+
+template <> struct Math<float> {
+  static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+  // tanh(x) = sign(x) (1 - e) / (1 + e), e = exp(-2|x|), with the hardware
+  // base-2 exponential; absolute error a few ulp of 1.
+  static __device__ __forceinline__ float tanh_(float x) {
+    const float m2log2e = -2.8853900817779268f;  // -2 / ln 2
+    float e = __builtin_amdgcn_exp2f(m2log2e * __builtin_fabsf(x));
+    float t = (1.0f - e) * __builtin_amdgcn_rcpf(1.0f + e);
+    return __builtin_copysignf(t, x);
+  }
+  static __device__ __forceinline__ bool finite(float x) { return __builtin_isfinite(x); }
+};
+
+template <> struct Math<double> {
+  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+  static __device__ __forceinline__ double tanh_(double x) { return tanh(x); }
+  static __device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
+};
+
+// ------------------------------------------------------- cross-lane moves
+// Lane i of a wave64 holds lattice column x0 + i.  from_right() returns the
+// value of lane i + 1 (column x + 1), from_left() the value of lane i - 1;
+// the end lanes receive 0.  Both are single DPP wave shifts.
+
+#define PF_DPP_WAVE_SHL1 0x130  // lane i reads lane i + 1
+#define PF_DPP_WAVE_SHR1 0x138  // lane i reads lane i - 1
+
+__device__ __forceinline__ float from_right(float v) {
+  return __builtin_amdgcn_update_dpp(0.0f, v, PF_DPP_WAVE_SHL1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float from_left(float v) {
+  return __builtin_amdgcn_update_dpp(0.0f, v, PF_DPP_WAVE_SHR1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ double from_right(double v) {
+  int2 a = __builtin_bit_cast(int2, v);
+  a.x = __builtin_amdgcn_update_dpp(0, a.x, PF_DPP_WAVE_SHL1, 0xF, 0xF, false);
+  a.y = __builtin_amdgcn_update_dpp(0, a.y, PF_DPP_WAVE_SHL1, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, a);
+}
+__device__ __forceinline__ double from_left(double v) {
+  int2 a = __builtin_bit_cast(int2, v);
+  a.x = __builtin_amdgcn_update_dpp(0, a.x, PF_DPP_WAVE_SHR1, 0xF, 0xF, false);
+  a.y = __builtin_amdgcn_update_dpp(0, a.y, PF_DPP_WAVE_SHR1, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, a);
+}
+__device__ __forceinline__ int from_right(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, PF_DPP_WAVE_SHL1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int from_left(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, PF_DPP_WAVE_SHR1, 0xF, 0xF, false);
+}
+
+// ------------------------------------------------------------- ghost maps
+// Lattice index i (possibly outside [0, n)) -> stored index.  PERIODIC wraps;
+// NOFLUX mirrors about the boundary face (-1 -> 0, -2 -> 1, n -> n-1, ...).
+__device__ __forceinline__ int ghost(int i, int n, int bc) {
+  if (bc == PF_BC_PERIODIC) {
+    int m = i % n;
+    return m < 0 ? m + n : m;
+  }
+  int p = 2 * n;
+  int m = i % p;
+  if (m < 0) m += p;
+  return m < n ? m : p - 1 - m;
+}
+
+// ------------------------------------------------ tip / fraction record
+
+struct TipAcc {
+  double y;       // best crossing height, -inf if none
+  long long idx;  // linear index of its lower cell (ties: smallest)
+  double fs;      // sum of (1 + phi)/2
+  unsigned bad;   // count of non-finite psi or U
+};
+
+__device__ __forceinline__ void tip_init(TipAcc &a) {
+  a.y = -__builtin_inf();
+  a.idx = 0x7fffffffffffffffLL;
+  a.fs = 0.0;
+  a.bad = 0u;
+}
+
+__device__ __forceinline__ void tip_merge(TipAcc &a, double y, long long idx, double fs,
+                                          unsigned bad) {
+  if (y > a.y || (y == a.y && idx < a.idx)) {
+    a.y = y;
+    a.idx = idx;
+  }
+  a.fs += fs;
+  a.bad += bad;
+}
+
+__device__ __forceinline__ double shfl_xor_d(double v, int m) {
+  return __shfl_xor(v, m, 64);
+}
+__device__ __forceinline__ long long shfl_xor_ll(long long v, int m) {
+  return __shfl_xor(v, m, 64);
+}
+
+// Butterfly over the 64 lanes; every lane ends with the wave total.
+__device__ __forceinline__ void tip_wave_reduce(TipAcc &a) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    double y = shfl_xor_d(a.y, m);
+    long long i = shfl_xor_ll(a.idx, m);
+    double f = shfl_xor_d(a.fs, m);
+    unsigned b = (unsigned)__shfl_xor((int)a.bad, m, 64);
+    tip_merge(a, y, i, f, b);
+  }
+}
+
+// Block reduction of one TipAcc per wave (blockDim = 64 * nwaves <= 1024),
+// then a grid-wide finish by the last block to arrive: it reduces every
+// block's partial in block order (deterministic) and calls finish(total).
+// `lds` needs room for 16 TipAcc.
+template <typename Finish>
+__device__ __forceinline__ void tip_block_and_grid(TipAcc a, TipAcc *partials,
+                                                   unsigned *counter, TipAcc *lds,
+                                                   Finish finish) {
+  tip_wave_reduce(a);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  if (lane == 0) lds[wave] = a;
+  __syncthreads();
+  __shared__ bool last;
+  if (threadIdx.x == 0) {
+    TipAcc b = lds[0];
+    for (int w = 1; w < nw; ++w) tip_merge(b, lds[w].y, lds[w].idx, lds[w].fs, lds[w].bad);
+    partials[blockIdx.x] = b;
+    __threadfence();
+    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+    last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  TipAcc c;
+  tip_init(c);
+  for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x) {
+    TipAcc p = partials[b];
+    tip_merge(c, p.y, p.idx, p.fs, p.bad);
+  }
+  // deterministic combine: lanes hold strided partial sums in fixed order
+  tip_wave_reduce(c);
+  if (lane == 0) lds[wave] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    TipAcc t = lds[0];
+    for (int w = 1; w < nw; ++w) tip_merge(t, lds[w].y, lds[w].idx, lds[w].fs, lds[w].bad);
+    finish(t);
+    *counter = 0u;  // ready for the next launch
+  }
+}
+
+}  // namespace pf

@@ -1,0 +1,124 @@
+// pf_internal.hpp -- host/device shared definitions of the phase-field
+// library: kernel argument blocks, device-resident frame and tip records,
+// and the launchers the C ABI calls.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/pf.h"
+
+namespace pf {
+
+// Moving-frame state of one time level, device resident.  `shift` counts
+// the rows the frame has moved for this level; `pending` = 1 means the stored
+// arrays still owe one downward shift, applied when they are next read.
+struct alignas(16) FrameState {
+  long long shift;
+  int pending;
+  int pad;
+};
+
+// Result of a grid-wide tip / solid-fraction / finiteness reduction.
+struct alignas(16) TipResult {
+  double y;          // crossing height in the frame, valid when found
+  long long idx;     // linear frame index of the cell below the crossing
+  double fs_sum;     // sum over cells of (1 + phi)/2
+  unsigned bad;      // number of non-finite psi or U values
+  int found;
+};
+
+struct TipAcc;  // per-block partial (pf_device.hpp)
+
+// Workspace pieces shared by every kernel of a solver.
+struct Reduce {
+  TipAcc *partials;
+  unsigned *counter;
+  TipResult *result;
+};
+
+// Physical constants of one step, precomputed on the host in FP64 and cast
+// to the working precision T.
+template <typename T>
+struct Coef {
+  T dt, k, omk, eps4, D, lambda;
+  T inv_h;          // 1/h
+  T cL1, cL2, cL3;  // shell weights of L over their prefactors
+  T cG1, cG2, cG3;  // shell weights of G over their prefactors
+  T cD1, cD2, cD3;  // shell weights of the divergence over their prefactors
+  T cStd;           // 1/h^2 (standard Laplacian of the eps4 remainder)
+  T inv_lT;         // 1/lT (frozen temperature)
+  T h;
+};
+
+template <typename T>
+struct Step2DArgs {
+  const T *psi_in, *U_in;
+  T *psi_out, *U_out;
+  const int8_t *grain;   // multi-grain only
+  const T *rot;          // multi-grain only: 4 per grain (r00, r01, r10, r11)
+  T r00, r01, r10, r11;  // single grain
+  int nx, ny, bcx, bcy;
+  int wout, nstrips, nsegs, seg;
+  Coef<T> c;
+  double hd, y0, Vp, dtd;
+  long long step;
+  int frame, shift_row;
+  const FrameState *frame_in;
+  FrameState *frame_out;
+  Reduce red;
+};
+
+template <typename T>
+struct Step3DArgs {
+  const T *psi_in, *U_in;
+  T *psi_out, *U_out;
+  const int8_t *grain;   // multi-grain only
+  const T *rot;          // 9 per grain, row-major crystal -> lab
+  T R[9];                // single grain
+  int nx, ny, nz, bcx, bcy, bcz;
+  int wout, nstrips, nzt, nsegs, seg, ztile;
+  Coef<T> c;
+  double hd, y0, Vp, dtd;
+  long long step;
+  int frame, shift_row;
+  const FrameState *frame_in;
+  FrameState *frame_out;
+  Reduce red;
+};
+
+template <typename T>
+struct ReduceArgs {
+  const T *psi, *U;
+  int nx, ny, nz;
+  double hd;
+  const FrameState *frame;  // pending shift of the arrays read
+  Reduce red;
+};
+
+// Launch geometry of the 2D step: wave64 strips of up to 60 output columns,
+// segments of `seg` rows.
+struct Geom2D {
+  int wout, nstrips, nsegs, seg, blocks;
+};
+Geom2D geom2d(int nx, int ny, int seg);
+
+struct Geom3D {
+  int wout, nstrips, ztile, nzt, nsegs, seg, blocks, threads;
+};
+Geom3D geom3d(int nx, int ny, int nz, int seg, int ztile);
+
+size_t tip_acc_bytes();
+int reduce_blocks(int nx, int ny, int nz);
+
+template <typename T>
+hipError_t launch_step2d(const Step2DArgs<T> &a, const Geom2D &g, bool frozen, bool reduce,
+                         bool multi, hipStream_t st);
+template <typename T>
+hipError_t launch_step3d(const Step3DArgs<T> &a, const Geom3D &g, bool frozen, bool reduce,
+                         bool multi, hipStream_t st);
+template <typename T>
+hipError_t launch_reduce(const ReduceArgs<T> &a, hipStream_t st);
+
+}  // namespace pf

@@ -1,0 +1,314 @@
+// step2d.hip -- fused psi/U explicit step on the 2D square lattice (gfx950).
+//
+// One launch advances psi and U by one explicit Euler step (Sec. 4.3.1):
+//   psi^{n+1} = psi^n + dt R_psi,  R_psi from Eq. PF_a with the isotropic
+//     Laplacian L_{s1,s2} (Eqs. 2D_L10, 2D_L01, 2D_L21), gradient square
+//     G_{s1,s2} (App. A, Eqs. Grad_10, Grad_11), the rotated cubic
+//     anisotropy (Eq. anis_function) whose eps4-linear terms use the standard
+//     <10> face fluxes (Sec. 2.2), and the frozen-temperature functions
+//     (Eqs. Thermal_F1, Thermal_F2);
+//   U^{n+1} = U^n + dt R_U,  R_U from Eq. PF_b with D~ div[(1-phi) grad U]
+//     and the approximated anti-trapping term div[alpha_A grad psi]
+//     (Eq. Anti_approx), both through the two-shell divergence
+//     D_{s1,s2} (Eqs. divergence_10, flux_10, divergence_11, flux_11).
+//
+// Schedule.  Each wave64 owns a strip of 64 lattice columns (60 outputs plus
+// a 2-column halo on each side) and a segment of `seg` rows, and marches up
+// the segment one row per iteration, holding a 3-row window of psi, U, phi
+// and alpha_A in registers.  x neighbours come from DPP wave shifts, so the
+// kernel uses no LDS and no barrier outside the final reduction.  With the
+// newest row r loaded, an iteration computes the y face flux r-1/2, the psi
+// rate of row r-1 (written out as psi^{n+1} and turned into alpha_A), and the
+// U update of row r-2, which needs alpha_A on rows r-3..r-1.  Fluxes shared
+// between neighbouring cells are computed once: x-direction ones are passed
+// across lanes, y-direction ones carried to the next row.  Optionally the same
+// pass reduces the tip, solid fraction and finiteness of state n (FP64).
+#include "pf_device.hpp"
+
+namespace pf {
+
+namespace {
+
+constexpr float kGradEps = 1e-12f;  // |grad psi|^2 below this: a_s = 1, no torque
+
+template <typename T>
+struct Rot2 {
+  T r00, r01, r10, r11;  // crystal -> lab
+};
+
+// a_s for lab gradient (gx, gy) (Eq. anis_function in the cubic form
+// 1 - 3 eps4 + 4 eps4 sum n'^4, n' = R^T n); 1 for a vanishing gradient.
+template <typename T>
+__device__ __forceinline__ T aniso_a(T gx, T gy, const Rot2<T> &R, T eps4) {
+  T g2 = gx * gx + gy * gy;
+  T r2 = Math<T>::rcp(g2 > T(kGradEps) ? g2 : T(kGradEps));
+  T cx = R.r00 * gx + R.r10 * gy;
+  T cy = R.r01 * gx + R.r11 * gy;
+  T cx2 = cx * cx, cy2 = cy * cy;
+  T s4 = (cx2 * cx2 + cy2 * cy2) * (r2 * r2);
+  T a = T(1) - T(3) * eps4 + T(4) * eps4 * s4;
+  return g2 > T(kGradEps) ? a : T(1);
+}
+
+// Component `comp` (0: x, 1: y) of the anisotropic flux
+// J = a^2 g + |g|^2 a da/dg at a face with lab gradient g:
+// J = R [ g' (a^2 - 16 eps4 a s4) + 16 eps4 a g'^3 / |g|^2 ],  g' = R^T g.
+template <typename T, int comp>
+__device__ __forceinline__ T aniso_flux(T gx, T gy, const Rot2<T> &R, T eps4) {
+  T g2 = gx * gx + gy * gy;
+  T r2 = Math<T>::rcp(g2 > T(kGradEps) ? g2 : T(kGradEps));
+  T cx = R.r00 * gx + R.r10 * gy;
+  T cy = R.r01 * gx + R.r11 * gy;
+  T cx2 = cx * cx, cy2 = cy * cy;
+  T s4 = (cx2 * cx2 + cy2 * cy2) * (r2 * r2);
+  T a = T(1) - T(3) * eps4 + T(4) * eps4 * s4;
+  T t = T(16) * eps4 * a;
+  T base = a * a - t * s4;
+  T tr = t * r2;
+  T jx = cx * (base + tr * cx2);
+  T jy = cy * (base + tr * cy2);
+  T j = comp == 0 ? R.r00 * jx + R.r01 * jy : R.r10 * jx + R.r11 * jy;
+  T plain = comp == 0 ? gx : gy;
+  return g2 > T(kGradEps) ? j : plain;
+}
+
+// Logical blocks -> hardware blocks so that each of the 8 XCDs (which take
+// consecutive hardware blocks round-robin) runs a contiguous range of strips
+// and shares their halo rows in its own L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int X = 8;
+  int q = nb / X, r = nb % X, x = b % X;
+  return x * q + (x < r ? x : r) + b / X;
+}
+
+template <typename T, bool kFrozen, bool kReduce, bool kMulti>
+__global__ __launch_bounds__(256) void step2d_kernel(Step2DArgs<T> a) {
+  using M = Math<T>;
+  const Coef<T> &c = a.c;
+  const int lane = threadIdx.x & 63;
+  const int lb = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int wave = lb * 4 + ((int)threadIdx.x >> 6);
+  const int nx = a.nx, ny = a.ny;
+
+  TipAcc acc;
+  tip_init(acc);
+
+  if (wave < a.nstrips * a.nsegs) {
+    const int strip = wave % a.nstrips, segi = wave / a.nstrips;
+    const int x = strip * a.wout - 2 + lane;
+    const int gx = ghost(x, nx, a.bcx);
+    const bool out_lane = lane >= 2 && lane < 2 + a.wout && x < nx;
+    const int y0 = segi * a.seg;
+    const int ye = min(y0 + a.seg, ny);
+    const int pend = a.frame ? a.frame_in->pending : 0;
+    T off = T(0);
+    if (kFrozen) {
+      long long s = a.frame ? a.frame_in->shift : 0;
+      off = (T)((double)s * a.hd - a.y0 - a.Vp * ((double)a.step * a.dtd));
+    }
+    const T sq2 = T(1.4142135623730951);
+    const T isq2 = T(0.70710678118654752);
+
+    auto prow = [&](int r) -> size_t {
+      int j = ghost(r, ny, a.bcy);
+      if (pend) j = min(j + 1, ny - 1);
+      return (size_t)j * (size_t)nx + (size_t)gx;
+    };
+    auto rot_of = [&](int g) -> Rot2<T> {
+      if (kMulti) {
+        const T *q = a.rot + 4 * g;
+        return Rot2<T>{q[0], q[1], q[2], q[3]};
+      }
+      return Rot2<T>{a.r00, a.r01, a.r10, a.r11};
+    };
+
+    // register window: S = row r-2, C = row r-1, N = row r (newest)
+    T pS = 0, pSW = 0, pSE = 0, pC = 0, pCW = 0, pCE = 0, pN = 0, pNW = 0, pNE = 0;
+    T uS = 0, uC = 0, uN = 0;
+    T fS = 0, fC = 0, fN = 0;
+    T aAS = 0, aAC = 0;
+    int gC = 0, gN = 0;
+    T FyS = 0;  // y face flux below row r-1
+    // carries of the divergence for the row pair below (q-1, q)
+    T cND = 0, c1D = 0, c2D = 0, cPD = 0;
+    T cNA = 0, c1A = 0, c2A = 0, cPA = 0;
+
+    size_t o = prow(y0 - 2);
+    T nxt_p = a.psi_in[o], nxt_u = a.U_in[o];
+    int nxt_g = kMulti ? (int)a.grain[o] : 0;
+
+    for (int r = y0 - 2; r <= ye + 1; ++r) {
+      pS = pC; pSW = pCW; pSE = pCE;
+      pC = pN; pCW = pNW; pCE = pNE;
+      uS = uC; uC = uN;
+      fS = fC; fC = fN;
+      aAS = aAC;
+      gC = gN;
+      pN = nxt_p; uN = nxt_u; gN = nxt_g;
+      if (r <= ye) {
+        size_t on = prow(r + 1);
+        nxt_p = a.psi_in[on];
+        nxt_u = a.U_in[on];
+        if (kMulti) nxt_g = (int)a.grain[on];
+      }
+      pNW = from_left(pN);
+      pNE = from_right(pN);
+      fN = M::tanh_(pN * isq2);
+
+      // y face between rows r-1 and r, grain of the lower cell
+      T FyN = T(0);
+      if (r >= y0 - 1) {
+        T gyn = (pN - pC) * c.inv_h;
+        T gxt = (pNE + pCE - pNW - pCW) * (T(0.25) * c.inv_h);
+        FyN = aniso_flux<T, 1>(gxt, gyn, rot_of(gC), c.eps4);
+      }
+
+      const int m = r - 1;
+      if (m >= y0 - 1) {
+        // ---------------- psi rate at row m (window rows S, C, N = m-1, m, m+1)
+        const Rot2<T> R = rot_of(gC);
+        T dE = pCE - pC, dW = pCW - pC, dN = pN - pC, dS = pS - pC;
+        T s10 = dE + dW + dN + dS;
+        T s11 = (pNE - pC) + (pNW - pC) + (pSE - pC) + (pSW - pC);
+        T L = c.cL1 * s10 + c.cL2 * s11;
+        T ex = pCE - pCW, ey = pN - pS;
+        T e1 = pNE - pSW, e2 = pSE - pNW;
+        T G = c.cG1 * (ex * ex + ey * ey) + c.cG2 * (e1 * e1 + e2 * e2);
+        T hh = T(0.5) * c.inv_h;
+        T ac = aniso_a(ex * hh, ey * hh, R, c.eps4);
+        T gxn = dE * c.inv_h;
+        T gyt = (pN + pNE - pS - pSE) * (T(0.25) * c.inv_h);
+        T FxE = aniso_flux<T, 0>(gxn, gyt, R, c.eps4);
+        T FxW = from_left(FxE);
+        T ac2 = ac * ac;
+        T Nn = (FxE - FxW + FyN - FyS) * c.inv_h - ac2 * (s10 * c.cStd);
+        T F1 = T(1), F2 = uC;
+        if (kFrozen) {
+          T zeta = (T)ghost(m, ny, a.bcy) * c.h + off;
+          F1 = T(1) - c.omk * zeta * c.inv_lT;
+          F2 = uC + zeta * c.inv_lT;
+        }
+        T ph = fC;
+        T omp = T(1) - ph * ph;
+        T rhs = ac2 * (L - sq2 * ph * G) + Nn + sq2 * (ph - c.lambda * omp * F2);
+        T rate = rhs * M::rcp(F1 * ac2);
+        T aA = (T(1) + c.omk * uC) * omp * rate * T(0.5);
+        if (a.bcx == PF_BC_NOFLUX) {  // mirrored columns copy their image
+          T fr = from_right(aA), fl = from_left(aA);
+          aA = (x == -1) ? fr : ((x == nx) ? fl : aA);
+        }
+        aAC = aA;
+        if (a.bcy == PF_BC_NOFLUX) {  // mirrored rows copy their image
+          if (m == 0) aAS = aAC;
+          if (m == ny) aAC = aAS;
+        }
+        if (out_lane && m >= y0 && m < ye) {
+          a.psi_out[(size_t)m * (size_t)nx + (size_t)x] = pC + c.dt * rate;
+          if (kReduce) {
+            double fc = (double)fC;
+            acc.fs += 0.5 * (1.0 + fc);
+            acc.bad += (M::finite(pC) && M::finite(uC)) ? 0u : 1u;
+            if (m <= ny - 2 && fC >= T(0) && fN < T(0)) {
+              double fn = (double)fN;
+              double yy = ((double)m + fc / (fc - fn)) * a.hd;
+              long long id = (long long)m * nx + x;
+              if (yy > acc.y || (yy == acc.y && id < acc.idx)) {
+                acc.y = yy;
+                acc.idx = id;
+              }
+            }
+          }
+        }
+      }
+      FyS = FyN;
+
+      const int q = r - 2;
+      if (q >= y0 - 1) {
+        // ---------------- divergences on the row pair (q, q+1) = (S, C)
+        // field D: alpha = 1 - phi, beta = U;  field A: alpha = alpha_A, beta = psi
+        T aq = T(1) - fS, aq1 = T(1) - fC;
+        T aE = from_right(aq), aNE = from_right(aq1);
+        T PD = (aq + aE + aq1 + aNE) * T(0.25);
+        T PDW = from_left(PD);
+        T uE = from_right(uS), uNE = from_right(uC), uNW = from_left(uC);
+        T fED = (aq + aE + PD + cPD) * (uE - uS);
+        T fND = (aq + aq1 + PD + PDW) * (uC - uS);
+        T d1D = PD * (uNE - uS), d2D = PDW * (uNW - uS);
+
+        T bE = from_right(aAS), bNE = from_right(aAC);
+        T PA = (aAS + bE + aAC + bNE) * T(0.25);
+        T PAW = from_left(PA);
+        T fEA = (aAS + bE + PA + cPA) * (pSE - pS);
+        T fNA = (aAS + aAC + PA + PAW) * (pC - pS);
+        T d1A = PA * (pCE - pS), d2A = PAW * (pCW - pS);
+
+        if (q >= y0) {
+          T fWD = -from_left(fED), fWA = -from_left(fEA);
+          T swD = -from_left(c1D), seD = -from_right(c2D);
+          T swA = -from_left(c1A), seA = -from_right(c2A);
+          T divD = c.cD1 * (fED + fWD + fND - cND) + c.cD2 * (d1D + d2D + swD + seD);
+          T divA = c.cD1 * (fEA + fWA + fNA - cNA) + c.cD2 * (d1A + d2A + swA + seA);
+          T rU = (c.D * divD + divA + sq2 * aAS) * M::rcp(T(1) + c.k - c.omk * fS);
+          if (out_lane && q < ye) a.U_out[(size_t)q * (size_t)nx + (size_t)x] = uS + c.dt * rU;
+        }
+        cND = fND; c1D = d1D; c2D = d2D; cPD = PD;
+        cNA = fNA; c1A = d1A; c2A = d2A; cPA = PA;
+      }
+    }
+  }
+
+  if (kReduce) {
+    __shared__ TipAcc lds[16];
+    const Step2DArgs<T> *ap = &a;
+    tip_block_and_grid(acc, a.red.partials, a.red.counter, lds, [ap](const TipAcc &t) {
+      TipResult *res = ap->red.result;
+      res->y = t.y;
+      res->idx = t.idx;
+      res->fs_sum = t.fs;
+      res->bad = t.bad;
+      res->found = t.y > -__builtin_inf() ? 1 : 0;
+      if (ap->frame) {
+        int sh = (res->found && t.y >= (double)ap->shift_row * ap->hd) ? 1 : 0;
+        ap->frame_out->shift = ap->frame_in->shift + sh;
+        ap->frame_out->pending = sh;
+      }
+    });
+  }
+}
+
+}  // namespace
+
+Geom2D geom2d(int nx, int ny, int seg) {
+  Geom2D g;
+  g.nstrips = (nx + 59) / 60;
+  g.wout = (nx + g.nstrips - 1) / g.nstrips;
+  g.seg = seg < 1 ? 1 : seg;
+  g.nsegs = (ny + g.seg - 1) / g.seg;
+  int waves = g.nstrips * g.nsegs;
+  g.blocks = (waves + 3) / 4;
+  return g;
+}
+
+template <typename T>
+hipError_t launch_step2d(const Step2DArgs<T> &a, const Geom2D &g, bool frozen, bool reduce,
+                         bool multi, hipStream_t st) {
+  dim3 grid(g.blocks), block(256);
+#define PF_L2(F, R, MU) \
+  hipLaunchKernelGGL((step2d_kernel<T, F, R, MU>), grid, block, 0, st, a)
+  if (frozen) {
+    if (reduce) { if (multi) PF_L2(true, true, true); else PF_L2(true, true, false); }
+    else { if (multi) PF_L2(true, false, true); else PF_L2(true, false, false); }
+  } else {
+    if (reduce) { if (multi) PF_L2(false, true, true); else PF_L2(false, true, false); }
+    else { if (multi) PF_L2(false, false, true); else PF_L2(false, false, false); }
+  }
+#undef PF_L2
+  return hipGetLastError();
+}
+
+template hipError_t launch_step2d<float>(const Step2DArgs<float> &, const Geom2D &, bool, bool,
+                                         bool, hipStream_t);
+template hipError_t launch_step2d<double>(const Step2DArgs<double> &, const Geom2D &, bool, bool,
+                                          bool, hipStream_t);
+
+}  // namespace pf

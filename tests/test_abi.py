@@ -1,0 +1,112 @@
+"""CPU checks of the C ABI: libpfiso.so loads, exports every function that
+include/pf.h declares, and its host-side validation rejects bad input with the
+documented codes before touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2110_12448_amd import pfiso
+from paper_2110_12448_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "pf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pf_[a-z_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(pfiso.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pfiso.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert lib.pf_version() == 1
+
+
+def test_struct_sizes_match_header_layout():
+    # pf_params: 6 int32, 3 doubles, 9 doubles, 3+3 int32, pointer -> 8-aligned
+    assert C.sizeof(pfiso.pf_params) == 4 * 6 + 8 * 3 + 8 * 9 + 4 * 6 + 8
+    assert C.sizeof(pfiso.pf_tip) == 8 + 8 + 4 + 4 + 8 + 8 * 6 + 8
+
+
+def _params(**over):
+    pr = wl.config_small_2d(30.0, n=32)
+    pr.update(over)
+    return pr
+
+
+def _create(pr, precision=pfiso.PF_F32):
+    lib = pfiso.load()
+    p, keep = pfiso.make_params(pr, precision)
+    psi = np.ascontiguousarray(pr["psi0"], dtype=np.float64)
+    U = np.ascontiguousarray(pr["U0"], dtype=np.float64)
+    g = pr.get("grain")
+    g = None if g is None else np.ascontiguousarray(g, dtype=np.int8)
+    ini = pfiso.pf_init(psi.ctypes.data_as(C.POINTER(C.c_double)),
+                        U.ctypes.data_as(C.POINTER(C.c_double)),
+                        None if g is None else g.ctypes.data_as(C.POINTER(C.c_int8)))
+    h = C.c_void_p()
+    rc = lib.pf_create(C.byref(p), C.byref(ini), None, 0, None, C.byref(h))
+    return rc, lib.pf_last_error().decode(), h
+
+
+def test_stable_dt_and_workspace():
+    lib = pfiso.load()
+    pr = _params()
+    p, keep = pfiso.make_params(pr)
+    dtmax = lib.pf_stable_dt(C.byref(p))
+    # h^2 / (2 dim max(D, 1/F1min)) with D = 2 and F1min > 1/2
+    assert dtmax == pytest.approx(0.8 ** 2 / 8.0)
+    ws = lib.pf_workspace_bytes(C.byref(p))
+    assert ws >= 4 * 32 * 32 * 4
+    p.precision = pfiso.PF_F64
+    assert lib.pf_workspace_bytes(C.byref(p)) >= 4 * 32 * 32 * 8
+
+
+@pytest.mark.parametrize("over,code,needle", [
+    (dict(dim=4), pfiso.PF_ERR_ARG, "dim"),
+    (dict(nx=3), pfiso.PF_ERR_ARG, ">= 4"),
+    (dict(k=1.5), pfiso.PF_ERR_ARG, "k must"),
+    (dict(eps4=0.2), pfiso.PF_ERR_ARG, "eps4"),
+    (dict(dt=0.2), pfiso.PF_ERR_UNSTABLE_DT, "stability"),
+    (dict(bc=(0, 1, 0), frame=1), pfiso.PF_ERR_ARG, "no-flux"),
+    (dict(frame=1, shift_row=40), pfiso.PF_ERR_ARG, "shift_row"),
+    (dict(lT=10.0, y0=-100.0), pfiso.PF_ERR_ARG, "F1"),
+    (dict(rot=np.diag([1.0, 1.0, -1.0])[None]), pfiso.PF_ERR_ARG, "improper"),
+    (dict(rot=wl.random_rotations(3, 1)), pfiso.PF_ERR_ARG, "about z"),
+])
+def test_create_rejects_bad_parameters(over, code, needle):
+    rc, msg, _ = _create(_params(**over))
+    assert rc == code and needle in msg, (rc, msg)
+
+
+def test_create_rejects_nonfinite_init():
+    pr = _params()
+    pr["psi0"] = pr["psi0"].copy()
+    pr["psi0"][3, 4] = np.nan
+    rc, msg, _ = _create(pr)
+    assert rc == pfiso.PF_ERR_NONFINITE
+
+
+def test_create_rejects_bad_grain():
+    pr = _params()
+    pr["grain"] = np.full(pr["psi0"].shape, 3, dtype=np.int8)
+    rc, msg, _ = _create(pr)
+    assert rc == pfiso.PF_ERR_ARG and "grain" in msg
+
+
+def test_frame_requires_columnar_grains():
+    pr = _params(frame=1, shift_row=16, rot=np.stack([wl.rotation_2d(0.0), wl.rotation_2d(20.0)]))
+    g = np.zeros(pr["psi0"].shape, dtype=np.int8)
+    g[10:, 5] = 1
+    pr["grain"] = g
+    rc, msg, _ = _create(pr)
+    assert rc == pfiso.PF_ERR_ARG and "along y" in msg

@@ -1,0 +1,186 @@
+"""GPU parity of the 2D fused step (through the C ABI) against the FP64 CPU
+oracle on identical seeded inputs."""
+import ctypes as C
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_12448_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+SQ2 = math.sqrt(2.0)
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+# FP64 kernel vs FP64 oracle: only summation order differs.
+TOL_F64 = 1e-10
+# FP32 kernel vs FP64 oracle after 100 steps: the stated bound.
+TOL_F32 = 1e-5
+
+
+def _pf():
+    from paper_2110_12448_amd import pfiso
+    return pfiso
+
+
+def run_gpu(pr, precision, nsteps, chunks=1):
+    pf = _pf()
+    print("gpu case: %dD %s prec=%d steps=%d" % (pr["dim"], (pr["nx"], pr["ny"], pr["nz"]),
+                                                precision, nsteps), flush=True)
+    s = pf.Solver(pr, precision=precision)
+    for _ in range(chunks):
+        s.step(nsteps // chunks)
+    phi, U, psi, g = s.read_fields()
+    tip = s.tip_state()
+    s.close()
+    return phi, U, psi, tip
+
+
+def run_oracle(pr, nsteps, **over):
+    p = oracle.Params.from_problem(pr, **over)
+    psi, U, st = oracle.step(p, pr["psi0"], pr["U0"], pr["grain"], nsteps)
+    phi = np.tanh(psi / SQ2)
+    return phi, U, psi, st, p
+
+
+def _cmp(a, b):
+    return float(np.max(np.abs(a - b)))
+
+
+@pytest.mark.parametrize("alpha0", [0.0, 30.0])
+@pytest.mark.parametrize("prec", [1, 0])
+def test_small_2d_parity(alpha0, prec):
+    """128 x 128, frozen gradient, disc seed with noise: 100 steps."""
+    pr = wl.config_small_2d(alpha0)
+    phi, U, psi, tip = run_gpu(pr, prec, 100)
+    ophi, oU, opsi, st, p = run_oracle(pr, 100)
+    dphi, dU = _cmp(phi, ophi), _cmp(U, oU)
+    print("max|dphi| %.3e max|dU| %.3e" % (dphi, dU))
+    tol = TOL_F64 if prec == 1 else TOL_F32
+    assert dphi <= tol and dU <= tol
+    ot = oracle.tip(p, ophi)
+    assert tip["found"] == 1 and ot["found"]
+    assert abs(tip["y_frame"] - ot["y"]) <= (1e-9 if prec == 1 else 1e-3)
+    assert tip["solid_fraction"] == pytest.approx(oracle.solid_fraction(p, ophi),
+                                                  abs=1e-12 if prec == 1 else 1e-6)
+
+
+def test_fp32_error_vs_storage_floor():
+    """The FP32 kernel's error is of the order of the error that FP32 storage
+    alone causes (oracle with per-step FP32 rounding of psi and U)."""
+    pr = wl.config_small_2d(30.0)
+    phi, U, _, _ = run_gpu(pr, 0, 100)
+    ophi, oU, _, _, _ = run_oracle(pr, 100)
+    fphi, fU, _, _, _ = run_oracle(pr, 100, round_f32=1)
+    floor = max(_cmp(fphi, ophi), _cmp(fU, oU))
+    err = max(_cmp(phi, ophi), _cmp(U, oU))
+    print("fp32 kernel error %.3e, storage floor %.3e" % (err, floor))
+    assert err <= 50 * floor + 1e-7
+
+
+EDGE = [
+    # (nx, ny, bc, thermal, scheme weights, grains, alpha0, eps4)
+    (61, 37, (0, 0, 0), "isothermal", wl.ISO_2D, 1, 17.0, 0.05),
+    (4, 5, (1, 1, 1), "isothermal", wl.STD_2D, 1, 30.0, 0.02),
+    (130, 70, (1, 0, 0), "frozen", wl.ISO_2D, 3, 0.0, 0.03),
+    (64, 64, (0, 0, 0), "frozen", wl.STD_2D, 1, 17.0, 0.02),
+    (121, 50, (1, 1, 1), "isothermal", (0.5, 0.5, 0.0), 2, 40.0, 0.04),
+    (7, 200, (0, 0, 0), "frozen", wl.ISO_2D, 1, 45.0, 0.02),
+]
+
+
+@pytest.mark.parametrize("case", range(len(EDGE)))
+def test_edge_cases_fp64(case):
+    nx, ny, bc, thermal, w, ng, a0, eps4 = EDGE[case]
+    rng = np.random.default_rng(case)
+    rot = np.stack([wl.rotation_2d(a0 + 13.0 * g) for g in range(ng)])
+    grain = rng.integers(0, ng, size=(ny, nx)).astype(np.int8) if ng > 1 else None
+    # a small seed in the middle keeps the signed distance continuous across
+    # periodic edges
+    pr = wl.problem(2, (nx, ny), thermal=thermal, bc=bc, rot=rot, grain=grain, eps4=eps4,
+                    seed_radius=min(nx, ny) / 5.0, y_front=(ny // 2) * 0.8, noise=0.02,
+                    seed=10 + case)
+    pr["w"] = tuple(w)
+    ophi, oU, opsi, st, p = run_oracle(pr, 50)
+    assert st.nonfinite == 0
+    phi, U, psi, tip = run_gpu(pr, 1, 50)
+    assert _cmp(phi, ophi) <= TOL_F64 and _cmp(U, oU) <= TOL_F64
+
+
+def test_moving_frame_parity():
+    """Frame shifts triggered from the fused tip reduction match the oracle's
+    lagged rule, row for row."""
+    pr = wl.config_small_2d(20.0, n=64, frame=1, shift_row=12)
+    pf = _pf()
+    s = pf.Solver(pr, precision=pf.PF_F64)
+    s.step(60)
+    phi, U, psi, g = s.read_fields()
+    shift, pend = s.frame_state()
+    tip = s.tip_state()
+    s.close()
+    ophi, oU, opsi, st, p = run_oracle(pr, 60)
+    assert st.shift > 5
+    assert shift == st.shift and tip["frame_shift"] == st.shift
+    assert _cmp(phi, ophi) <= TOL_F64 and _cmp(U, oU) <= TOL_F64
+    ot = oracle.tip(p, ophi)
+    assert tip["y_lab"] == pytest.approx(ot["y"] + st.shift * p.h, abs=1e-9)
+
+
+def test_deterministic_fp32():
+    pr = wl.config_small_2d(30.0)
+    a = run_gpu(pr, 0, 50)
+    b = run_gpu(pr, 0, 50, chunks=5)
+    assert np.array_equal(a[2], b[2]) and np.array_equal(a[1], b[1])
+
+
+def test_directional_full_size_fp32():
+    """1024 x 2048 FP32 with the moving frame, in the launch configuration of
+    the benchmark: every cell after 20 steps against the oracle."""
+    pr = wl.config_directional_2d()
+    phi, U, psi, tip = run_gpu(pr, 0, 20)
+    ophi, oU, opsi, st, p = run_oracle(pr, 20)
+    assert _cmp(phi, ophi) <= TOL_F32 and _cmp(U, oU) <= TOL_F32
+    ot = oracle.tip(p, ophi)
+    assert abs(tip["y_frame"] - ot["y"]) < 1e-3
+
+
+def test_tip_after_10k_steps():
+    """Tip within 0.05 W of the oracle after 10^4 steps (128 x 128, frame at
+    row 64); oracle values stored by tests/golden/make_tip_golden.py."""
+    gold = json.load(open(os.path.join(HERE, "golden", "tip_small_2d_10k.json")))
+    pf = _pf()
+    for case in gold["cases"]:
+        prec = pf.PF_F64 if case["round_f32"] == 0 else pf.PF_F32
+        pr = wl.config_small_2d(case["alpha0_deg"], frame=1, shift_row=64)
+        s = pf.Solver(pr, precision=prec)
+        s.step(gold["nsteps"])
+        t = s.tip_state()
+        s.close()
+        print(case, {k: t[k] for k in ("x", "y_lab", "frame_shift", "solid_fraction")})
+        assert abs(t["y_lab"] - case["y_lab"]) <= 0.05
+        assert abs(t["x"] - case["x"]) <= 0.05 + 1e-9 or prec == pf.PF_F32
+
+
+def test_nonfinite_detected():
+    """A NaN written into the device state (from the host) is reported by
+    pf_tip_state as PF_ERR_NONFINITE."""
+    pf = _pf()
+    pr = wl.config_small_2d(0.0, n=32)
+    s = pf.Solver(pr, precision=pf.PF_F32)
+    s.step(2)
+    s.synchronize()
+    psi_ptr, _ = s.device_fields()
+    hip = C.CDLL("libamdhip64.so.7")
+    nan = np.array([np.nan], dtype=np.float32)
+    rc = hip.hipMemcpy(C.c_void_p(psi_ptr + 4 * 100), nan.ctypes.data_as(C.c_void_p),
+                       C.c_size_t(4), C.c_int(1))
+    assert rc == 0
+    t = s.tip_state(allow_nonfinite=True)
+    assert t["nonfinite"] == 1
+    with pytest.raises(pf.PFError) as e:
+        s.tip_state()
+    assert e.value.code == pf.PF_ERR_NONFINITE
+    s.close()
