@@ -157,6 +157,11 @@ int pf_device_fields(pf_solver *s, void **psi, void **U);
  * downward shift (applied on the fly by the next step and by the readers). */
 int pf_frame_state(pf_solver *s, int64_t *shift, int32_t *pending);
 
+/* Launch geometry of the step kernels: rows per wave segment (2D and 3D,
+ * 4..256) and z rows per workgroup (3D, 1..8; ignored in 2D).  Results do not
+ * depend on it (only the work split changes); used by the tile autotuner. */
+int pf_tune(pf_solver *s, int32_t rows_per_segment, int32_t z_tile);
+
 /* Release the solver (and its workspace if the library allocated it). */
 void pf_destroy(pf_solver *s);
 

@@ -31,7 +31,15 @@ int fail(int code, const std::string &msg) {
 
 // thin-interface constant a2 = 47/75 (Sec. 2.1): default lambda = D~ / a2
 constexpr double kA2 = 47.0 / 75.0;
-constexpr int kDefaultSeg2D = 16;
+// Rows per wave segment in 2D: about 4.5 waves per SIMD on the 1024 SIMDs of
+// an MI355X when the lattice is small (short segments cost a 2-row psi
+// recompute each), up to 32 rows when there is work to spare (sweep on
+// 1024x2048 and 8192x8192 lattices).
+int default_seg2d(int nx, int ny) {
+  long long strips = (nx + 59) / 60;
+  long long seg = strips * ny / 4608;
+  return (int)(seg < 8 ? 8 : (seg > 32 ? 32 : seg));
+}
 constexpr int kDefaultSeg3D = 16;
 constexpr int kDefaultZTile3D = 4;
 
@@ -72,7 +80,7 @@ int max_step_blocks(const pf_params *p, int seg, int ztile) {
 }
 
 struct Layout {
-  size_t psi[2], U[2], grain, rot, frame[2], partials, counter, result, total;
+  size_t psi[2], U[2], grain, rot, frame[3], partials, counter, result, total;
 };
 
 Layout layout_of(const pf_params *p) {
@@ -84,7 +92,7 @@ Layout layout_of(const pf_params *p) {
   for (int i = 0; i < 2; ++i) { L.U[i] = o; o += align256(n * es); }
   L.grain = o; o += align256(p->n_grains > 1 ? n : 1);
   L.rot = o; o += align256((size_t)(p->n_grains > 0 ? p->n_grains : 1) * 9 * es);
-  for (int i = 0; i < 2; ++i) { L.frame[i] = o; o += 256; }
+  for (int i = 0; i < 3; ++i) { L.frame[i] = o; o += 256; }
   // per-block partials: enough for the finest segmentation the step accepts
   int nb = std::max(max_step_blocks(p, 4, 1), reduce_blocks(p->nx, p->ny, p->dim == 3 ? p->nz : 1));
   L.partials = o; o += align256((size_t)(nb + 64) * tip_acc_bytes());
@@ -101,8 +109,9 @@ int validate(const pf_params *p) {
     return fail(PF_ERR_ARG, "every lattice side must be >= 4");
   if ((double)p->nx * p->ny * (p->dim == 3 ? p->nz : 1) > 4.0e9)
     return fail(PF_ERR_ARG, "lattice larger than 4e9 cells");
-  if ((long long)p->nx * p->ny > 2147483647LL / 2)
-    return fail(PF_ERR_ARG, "x-y plane too large");
+  if ((long long)p->nx * p->ny > 2147483647LL / 2 ||
+      (long long)p->ny * (p->dim == 3 ? p->nz : 1) > 2147483647LL / 2)
+    return fail(PF_ERR_ARG, "x-y plane or y-z plane too large");
   if (p->precision != PF_F32 && p->precision != PF_F64)
     return fail(PF_ERR_ARG, "precision must be PF_F32 or PF_F64");
   if (p->scheme < PF_SCHEME_ISO || p->scheme > PF_SCHEME_WEIGHTS)
@@ -168,7 +177,7 @@ struct pf_solver {
   bool own;
   Layout L;
   int cur;    // current field buffers
-  int fcur;   // current frame record
+  int fcur;   // current frame record (0..2, advances with the frame on)
   long long step;
   int seg, ztile;
   bool have_prev;
@@ -191,6 +200,9 @@ Coef<T> coef_of(const pf_solver *s) {
   c.k = (T)p.k;
   c.omk = (T)(1.0 - p.k);
   c.eps4 = (T)p.eps4;
+  c.an0 = (T)(1.0 - 3.0 * p.eps4);
+  c.an4 = (T)(4.0 * p.eps4);
+  c.an16 = (T)(16.0 * p.eps4);
   c.D = (T)p.D;
   c.lambda = (T)s->lambda;
   c.inv_h = (T)(1.0 / h);
@@ -260,10 +272,8 @@ int step_impl(pf_solver *s, long long nsteps) {
   const bool frozen = p.lT > 0.0;
   const bool reduce = p.frame != 0;
   const bool multi = p.n_grains > 1;
-  Reduce red{reinterpret_cast<TipAcc *>(s->ws + s->L.partials),
-             reinterpret_cast<unsigned *>(s->ws + s->L.counter),
-             reinterpret_cast<TipResult *>(s->ws + s->L.result)};
   const Coef<T> c = coef_of<T>(s);
+  auto frec = [&](int i) { return reinterpret_cast<FrameState *>(s->ws + s->L.frame[i % 3]); };
   if (p.dim == 2) {
     Step2DArgs<T> a;
     memset(&a, 0, sizeof(a));
@@ -276,18 +286,18 @@ int step_impl(pf_solver *s, long long nsteps) {
     a.c = c;
     a.hd = p.h; a.y0 = p.y0; a.Vp = p.Vp; a.dtd = s->dt;
     a.frame = p.frame; a.shift_row = p.shift_row;
-    a.red = red;
     for (long long i = 0; i < nsteps; ++i) {
       a.psi_in = field<T>(s, s->L.psi[s->cur]);
       a.U_in = field<T>(s, s->L.U[s->cur]);
       a.psi_out = field<T>(s, s->L.psi[1 - s->cur]);
       a.U_out = field<T>(s, s->L.U[1 - s->cur]);
-      a.frame_in = reinterpret_cast<const FrameState *>(s->ws + s->L.frame[s->fcur]);
-      a.frame_out = reinterpret_cast<FrameState *>(s->ws + s->L.frame[reduce ? 1 - s->fcur : s->fcur]);
+      a.frame_in = frec(s->fcur);
+      a.frame_out = frec(s->fcur + 1);
+      a.frame_clear = frec(s->fcur + 2);
       a.step = s->step;
       PF_HIP(launch_step2d<T>(a, g, frozen, reduce, multi, s->stream));
       s->cur = 1 - s->cur;
-      if (reduce) s->fcur = 1 - s->fcur;
+      if (reduce) s->fcur = (s->fcur + 1) % 3;
       s->step += 1;
     }
   } else {
@@ -304,18 +314,18 @@ int step_impl(pf_solver *s, long long nsteps) {
     a.c = c;
     a.hd = p.h; a.y0 = p.y0; a.Vp = p.Vp; a.dtd = s->dt;
     a.frame = p.frame; a.shift_row = p.shift_row;
-    a.red = red;
     for (long long i = 0; i < nsteps; ++i) {
       a.psi_in = field<T>(s, s->L.psi[s->cur]);
       a.U_in = field<T>(s, s->L.U[s->cur]);
       a.psi_out = field<T>(s, s->L.psi[1 - s->cur]);
       a.U_out = field<T>(s, s->L.U[1 - s->cur]);
-      a.frame_in = reinterpret_cast<const FrameState *>(s->ws + s->L.frame[s->fcur]);
-      a.frame_out = reinterpret_cast<FrameState *>(s->ws + s->L.frame[reduce ? 1 - s->fcur : s->fcur]);
+      a.frame_in = frec(s->fcur);
+      a.frame_out = frec(s->fcur + 1);
+      a.frame_clear = frec(s->fcur + 2);
       a.step = s->step;
       PF_HIP(launch_step3d<T>(a, g, frozen, reduce, multi, s->stream));
       s->cur = 1 - s->cur;
-      if (reduce) s->fcur = 1 - s->fcur;
+      if (reduce) s->fcur = (s->fcur + 1) % 3;
       s->step += 1;
     }
   }
@@ -430,7 +440,7 @@ int pf_create(const pf_params *p, const pf_init *init, void *workspace, size_t w
   s->cur = 0;
   s->fcur = 0;
   s->step = 0;
-  s->seg = p->dim == 2 ? kDefaultSeg2D : kDefaultSeg3D;
+  s->seg = p->dim == 2 ? default_seg2d(p->nx, p->ny) : kDefaultSeg3D;
   s->ztile = kDefaultZTile3D;
   s->have_prev = false;
   if (workspace) {
@@ -462,6 +472,7 @@ int pf_create(const pf_params *p, const pf_init *init, void *workspace, size_t w
     FrameState z{0, 0, 0};
     if (hipMemcpy(s->ws + L.frame[0], &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(s->ws + L.frame[1], &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(s->ws + L.frame[2], &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(s->ws + L.counter, 0, 256) != hipSuccess)
       r2 = fail(PF_ERR_DEVICE, "state initialisation failed");
   }
@@ -515,7 +526,7 @@ int pf_tip_state(pf_solver *s, pf_tip *out) {
   t.t = (double)s->step * s->dt;
   t.found = r.found;
   t.nonfinite = r.bad ? 1 : 0;
-  t.frame_shift = fr.shift;
+  t.frame_shift = fr.base + fr.pending;
   t.solid_fraction = r.fs_sum / (double)s->n;
   if (r.found) {
     const long long nx = p.nx, ny = p.ny;
@@ -523,7 +534,7 @@ int pf_tip_state(pf_solver *s, pf_tip *out) {
     t.x = (double)(r.idx % nx) * p.h;
     t.z = p.dim == 3 ? (double)(r.idx / (nx * ny)) * p.h : 0.0;
     t.y_frame = r.y;
-    t.y_lab = r.y + (double)fr.shift * p.h;
+    t.y_lab = r.y + (double)t.frame_shift * p.h;
     if (s->have_prev && t.t > s->prev_t) t.velocity = (t.y_lab - s->prev_y) / (t.t - s->prev_t);
     s->have_prev = true;
     s->prev_t = t.t;
@@ -548,8 +559,19 @@ int pf_frame_state(pf_solver *s, int64_t *shift, int32_t *pending) {
   FrameState fr;
   PF_HIP(hipStreamSynchronize(s->stream));
   PF_HIP(hipMemcpy(&fr, s->ws + s->L.frame[s->fcur], sizeof(fr), hipMemcpyDeviceToHost));
-  if (shift) *shift = fr.shift;
+  if (shift) *shift = fr.base + fr.pending;
   if (pending) *pending = fr.pending;
+  return PF_OK;
+}
+
+int pf_tune(pf_solver *s, int32_t rows_per_segment, int32_t z_tile) {
+  if (!s) return fail(PF_ERR_ARG, "solver is NULL");
+  if (rows_per_segment < 4 || rows_per_segment > 256)
+    return fail(PF_ERR_ARG, "rows_per_segment must lie in [4, 256]");
+  if (s->p.dim == 3 && (z_tile < 1 || z_tile > 8))
+    return fail(PF_ERR_ARG, "z_tile must lie in [1, 8]");
+  s->seg = rows_per_segment;
+  if (s->p.dim == 3) s->ztile = z_tile;
   return PF_OK;
 }
 

@@ -42,28 +42,28 @@ template <> struct Math<double> {
 #define PF_DPP_WAVE_SHR1 0x138  // lane i reads lane i - 1
 
 __device__ __forceinline__ float from_right(float v) {
-  return __builtin_amdgcn_update_dpp(0.0f, v, PF_DPP_WAVE_SHL1, 0xF, 0xF, false);
+  return __builtin_amdgcn_update_dpp(0.0f, v, PF_DPP_WAVE_SHL1, 0xF, 0xF, true);
 }
 __device__ __forceinline__ float from_left(float v) {
-  return __builtin_amdgcn_update_dpp(0.0f, v, PF_DPP_WAVE_SHR1, 0xF, 0xF, false);
+  return __builtin_amdgcn_update_dpp(0.0f, v, PF_DPP_WAVE_SHR1, 0xF, 0xF, true);
 }
 __device__ __forceinline__ double from_right(double v) {
   int2 a = __builtin_bit_cast(int2, v);
-  a.x = __builtin_amdgcn_update_dpp(0, a.x, PF_DPP_WAVE_SHL1, 0xF, 0xF, false);
-  a.y = __builtin_amdgcn_update_dpp(0, a.y, PF_DPP_WAVE_SHL1, 0xF, 0xF, false);
+  a.x = __builtin_amdgcn_update_dpp(0, a.x, PF_DPP_WAVE_SHL1, 0xF, 0xF, true);
+  a.y = __builtin_amdgcn_update_dpp(0, a.y, PF_DPP_WAVE_SHL1, 0xF, 0xF, true);
   return __builtin_bit_cast(double, a);
 }
 __device__ __forceinline__ double from_left(double v) {
   int2 a = __builtin_bit_cast(int2, v);
-  a.x = __builtin_amdgcn_update_dpp(0, a.x, PF_DPP_WAVE_SHR1, 0xF, 0xF, false);
-  a.y = __builtin_amdgcn_update_dpp(0, a.y, PF_DPP_WAVE_SHR1, 0xF, 0xF, false);
+  a.x = __builtin_amdgcn_update_dpp(0, a.x, PF_DPP_WAVE_SHR1, 0xF, 0xF, true);
+  a.y = __builtin_amdgcn_update_dpp(0, a.y, PF_DPP_WAVE_SHR1, 0xF, 0xF, true);
   return __builtin_bit_cast(double, a);
 }
 __device__ __forceinline__ int from_right(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, PF_DPP_WAVE_SHL1, 0xF, 0xF, false);
+  return __builtin_amdgcn_update_dpp(0, v, PF_DPP_WAVE_SHL1, 0xF, 0xF, true);
 }
 __device__ __forceinline__ int from_left(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, PF_DPP_WAVE_SHR1, 0xF, 0xF, false);
+  return __builtin_amdgcn_update_dpp(0, v, PF_DPP_WAVE_SHR1, 0xF, 0xF, true);
 }
 
 // ------------------------------------------------------------- ghost maps
@@ -78,6 +78,14 @@ __device__ __forceinline__ int ghost(int i, int n, int bc) {
   int m = i % p;
   if (m < 0) m += p;
   return m < n ? m : p - 1 - m;
+}
+
+// Same map for indices within one period of the lattice (-n <= i < 2n), with
+// no division: used for row indices inside the time-step loops.
+__device__ __forceinline__ int ghost_near(int i, int n, int bc) {
+  if (i < 0) return bc == PF_BC_PERIODIC ? i + n : -i - 1;
+  if (i >= n) return bc == PF_BC_PERIODIC ? i - n : 2 * n - 1 - i;
+  return i;
 }
 
 // ------------------------------------------------ tip / fraction record

@@ -11,11 +11,14 @@
 
 namespace pf {
 
-// Moving-frame state of one time level, device resident.  `shift` counts
-// the rows the frame has moved for this level; `pending` = 1 means the stored
-// arrays still owe one downward shift, applied when they are next read.
+// Moving-frame record of one time level, device resident.  The rows the
+// frame has moved for this level are base + pending; pending = 1 means the
+// stored arrays still owe one downward shift, applied when they are next
+// read.  Step n reads record n % 3, publishes base and ORs pending into record
+// (n+1) % 3, and clears pending of record (n+2) % 3 for step n+1: no grid-wide
+// synchronisation or fence is needed inside a step.
 struct alignas(16) FrameState {
-  long long shift;
+  long long base;
   int pending;
   int pad;
 };
@@ -43,6 +46,7 @@ struct Reduce {
 template <typename T>
 struct Coef {
   T dt, k, omk, eps4, D, lambda;
+  T an0, an4, an16;  // 1 - 3 eps4, 4 eps4, 16 eps4 (cubic a_s and its torque)
   T inv_h;          // 1/h
   T cL1, cL2, cL3;  // shell weights of L over their prefactors
   T cG1, cG2, cG3;  // shell weights of G over their prefactors
@@ -66,8 +70,7 @@ struct Step2DArgs {
   long long step;
   int frame, shift_row;
   const FrameState *frame_in;
-  FrameState *frame_out;
-  Reduce red;
+  FrameState *frame_out, *frame_clear;
 };
 
 template <typename T>
@@ -84,8 +87,7 @@ struct Step3DArgs {
   long long step;
   int frame, shift_row;
   const FrameState *frame_in;
-  FrameState *frame_out;
-  Reduce red;
+  FrameState *frame_out, *frame_clear;
 };
 
 template <typename T>

@@ -18,13 +18,13 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs<T> a) {
   using M = Math<T>;
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const int pend = a.frame->pending;
-  const long long lines = (long long)ny * nz;
+  const int lines = ny * nz;
   const T isq2 = T(0.70710678118654752);
   TipAcc acc;
   tip_init(acc);
-  for (long long line = blockIdx.x; line < lines; line += gridDim.x) {
-    const int j = (int)(line % ny);
-    const int l = (int)(line / ny);
+  for (int line = blockIdx.x; line < lines; line += gridDim.x) {
+    const int j = line % ny;
+    const int l = line / ny;
     const int jp = pend ? min(j + 1, ny - 1) : j;
     const int jq = pend ? min(j + 2, ny - 1) : j + 1;
     const size_t base = (size_t)l * (size_t)ny * (size_t)nx;
@@ -65,8 +65,9 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs<T> a) {
 size_t tip_acc_bytes() { return sizeof(TipAcc); }
 
 int reduce_blocks(int nx, int ny, int nz) {
+  (void)nx;
   long long lines = (long long)ny * nz;
-  return (int)(lines < 2048 ? lines : 2048);
+  return (int)(lines < 256 ? lines : 256);  // one block per CU: few grid-wide fences
 }
 
 template <typename T>

@@ -23,6 +23,8 @@
 // between neighbouring cells are computed once: x-direction ones are passed
 // across lanes, y-direction ones carried to the next row.  Optionally the same
 // pass reduces the tip, solid fraction and finiteness of state n (FP64).
+#include <type_traits>
+
 #include "pf_device.hpp"
 
 namespace pf {
@@ -39,14 +41,14 @@ struct Rot2 {
 // a_s for lab gradient (gx, gy) (Eq. anis_function in the cubic form
 // 1 - 3 eps4 + 4 eps4 sum n'^4, n' = R^T n); 1 for a vanishing gradient.
 template <typename T>
-__device__ __forceinline__ T aniso_a(T gx, T gy, const Rot2<T> &R, T eps4) {
+__device__ __forceinline__ T aniso_a(T gx, T gy, const Rot2<T> &R, const Coef<T> &c) {
   T g2 = gx * gx + gy * gy;
   T r2 = Math<T>::rcp(g2 > T(kGradEps) ? g2 : T(kGradEps));
   T cx = R.r00 * gx + R.r10 * gy;
   T cy = R.r01 * gx + R.r11 * gy;
   T cx2 = cx * cx, cy2 = cy * cy;
   T s4 = (cx2 * cx2 + cy2 * cy2) * (r2 * r2);
-  T a = T(1) - T(3) * eps4 + T(4) * eps4 * s4;
+  T a = c.an0 + c.an4 * s4;
   return g2 > T(kGradEps) ? a : T(1);
 }
 
@@ -54,15 +56,15 @@ __device__ __forceinline__ T aniso_a(T gx, T gy, const Rot2<T> &R, T eps4) {
 // J = a^2 g + |g|^2 a da/dg at a face with lab gradient g:
 // J = R [ g' (a^2 - 16 eps4 a s4) + 16 eps4 a g'^3 / |g|^2 ],  g' = R^T g.
 template <typename T, int comp>
-__device__ __forceinline__ T aniso_flux(T gx, T gy, const Rot2<T> &R, T eps4) {
+__device__ __forceinline__ T aniso_flux(T gx, T gy, const Rot2<T> &R, const Coef<T> &c) {
   T g2 = gx * gx + gy * gy;
   T r2 = Math<T>::rcp(g2 > T(kGradEps) ? g2 : T(kGradEps));
   T cx = R.r00 * gx + R.r10 * gy;
   T cy = R.r01 * gx + R.r11 * gy;
   T cx2 = cx * cx, cy2 = cy * cy;
   T s4 = (cx2 * cx2 + cy2 * cy2) * (r2 * r2);
-  T a = T(1) - T(3) * eps4 + T(4) * eps4 * s4;
-  T t = T(16) * eps4 * a;
+  T a = c.an0 + c.an4 * s4;
+  T t = c.an16 * a;
   T base = a * a - t * s4;
   T tr = t * r2;
   T jx = cx * (base + tr * cx2);
@@ -87,11 +89,11 @@ __global__ __launch_bounds__(256) void step2d_kernel(Step2DArgs<T> a) {
   const Coef<T> &c = a.c;
   const int lane = threadIdx.x & 63;
   const int lb = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-  const int wave = lb * 4 + ((int)threadIdx.x >> 6);
+  // wave-uniform: keeps strip, segment and row counters in scalar registers
+  const int wave = lb * 4 + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int nx = a.nx, ny = a.ny;
 
-  TipAcc acc;
-  tip_init(acc);
+  bool over_any = false;
 
   if (wave < a.nstrips * a.nsegs) {
     const int strip = wave % a.nstrips, segi = wave / a.nstrips;
@@ -101,16 +103,16 @@ __global__ __launch_bounds__(256) void step2d_kernel(Step2DArgs<T> a) {
     const int y0 = segi * a.seg;
     const int ye = min(y0 + a.seg, ny);
     const int pend = a.frame ? a.frame_in->pending : 0;
+    const long long shift = a.frame ? a.frame_in->base + pend : 0;
     T off = T(0);
-    if (kFrozen) {
-      long long s = a.frame ? a.frame_in->shift : 0;
-      off = (T)((double)s * a.hd - a.y0 - a.Vp * ((double)a.step * a.dtd));
-    }
+    if (kFrozen) off = (T)((double)shift * a.hd - a.y0 - a.Vp * ((double)a.step * a.dtd));
+    const double ythr = (double)a.shift_row * a.hd;
+    bool over = false;  // this lane saw a crossing at or above the shift row
     const T sq2 = T(1.4142135623730951);
     const T isq2 = T(0.70710678118654752);
 
     auto prow = [&](int r) -> size_t {
-      int j = ghost(r, ny, a.bcy);
+      int j = ghost_near(r, ny, a.bcy);
       if (pend) j = min(j + 1, ny - 1);
       return (size_t)j * (size_t)nx + (size_t)gx;
     };
@@ -133,39 +135,53 @@ __global__ __launch_bounds__(256) void step2d_kernel(Step2DArgs<T> a) {
     T cND = 0, c1D = 0, c2D = 0, cPD = 0;
     T cNA = 0, c1A = 0, c2A = 0, cPA = 0;
 
-    size_t o = prow(y0 - 2);
-    T nxt_p = a.psi_in[o], nxt_u = a.U_in[o];
-    int nxt_g = kMulti ? (int)a.grain[o] : 0;
+    // rows r, r+1, r+2 in flight (loads issued two iterations ahead)
+    T lp0, lu0, lp1, lu1, lp2, lu2;
+    int lg0 = 0, lg1 = 0, lg2 = 0;
+    {
+      size_t o0 = prow(y0 - 2), o1 = prow(y0 - 1), o2 = prow(y0);
+      lp0 = a.psi_in[o0]; lu0 = a.U_in[o0];
+      lp1 = a.psi_in[o1]; lu1 = a.U_in[o1];
+      lp2 = a.psi_in[o2]; lu2 = a.U_in[o2];
+      if (kMulti) { lg0 = a.grain[o0]; lg1 = a.grain[o1]; lg2 = a.grain[o2]; }
+    }
 
-    for (int r = y0 - 2; r <= ye + 1; ++r) {
+    // One row of the pipeline.  P is the pipeline phase: 0 loads only (row
+    // y0-2), 1 adds the y face flux, 2 the psi rate of row y0-1, 3 the first
+    // stored psi row and the divergence carries of the pair (y0-1, y0), 4 is
+    // the steady state with every stage active.
+    auto iter = [&](auto phase, int r) {
+      constexpr int P = decltype(phase)::value;
       pS = pC; pSW = pCW; pSE = pCE;
       pC = pN; pCW = pNW; pCE = pNE;
       uS = uC; uC = uN;
       fS = fC; fC = fN;
       aAS = aAC;
       gC = gN;
-      pN = nxt_p; uN = nxt_u; gN = nxt_g;
-      if (r <= ye) {
-        size_t on = prow(r + 1);
-        nxt_p = a.psi_in[on];
-        nxt_u = a.U_in[on];
-        if (kMulti) nxt_g = (int)a.grain[on];
+      pN = lp0; uN = lu0; gN = lg0;
+      lp0 = lp1; lu0 = lu1; lg0 = lg1;
+      lp1 = lp2; lu1 = lu2; lg1 = lg2;
+      if (r + 3 <= ye + 1) {
+        size_t on = prow(r + 3);
+        lp2 = a.psi_in[on];
+        lu2 = a.U_in[on];
+        if (kMulti) lg2 = a.grain[on];
       }
       pNW = from_left(pN);
       pNE = from_right(pN);
       fN = M::tanh_(pN * isq2);
+      if constexpr (P == 0) return;
 
       // y face between rows r-1 and r, grain of the lower cell
-      T FyN = T(0);
-      if (r >= y0 - 1) {
+      T FyN;
+      {
         T gyn = (pN - pC) * c.inv_h;
         T gxt = (pNE + pCE - pNW - pCW) * (T(0.25) * c.inv_h);
-        FyN = aniso_flux<T, 1>(gxt, gyn, rot_of(gC), c.eps4);
+        FyN = aniso_flux<T, 1>(gxt, gyn, rot_of(gC), c);
       }
-
-      const int m = r - 1;
-      if (m >= y0 - 1) {
+      if constexpr (P >= 2) {
         // ---------------- psi rate at row m (window rows S, C, N = m-1, m, m+1)
+        const int m = r - 1;
         const Rot2<T> R = rot_of(gC);
         T dE = pCE - pC, dW = pCW - pC, dN = pN - pC, dS = pS - pC;
         T s10 = dE + dW + dN + dS;
@@ -175,16 +191,16 @@ __global__ __launch_bounds__(256) void step2d_kernel(Step2DArgs<T> a) {
         T e1 = pNE - pSW, e2 = pSE - pNW;
         T G = c.cG1 * (ex * ex + ey * ey) + c.cG2 * (e1 * e1 + e2 * e2);
         T hh = T(0.5) * c.inv_h;
-        T ac = aniso_a(ex * hh, ey * hh, R, c.eps4);
+        T ac = aniso_a(ex * hh, ey * hh, R, c);
         T gxn = dE * c.inv_h;
         T gyt = (pN + pNE - pS - pSE) * (T(0.25) * c.inv_h);
-        T FxE = aniso_flux<T, 0>(gxn, gyt, R, c.eps4);
+        T FxE = aniso_flux<T, 0>(gxn, gyt, R, c);
         T FxW = from_left(FxE);
         T ac2 = ac * ac;
         T Nn = (FxE - FxW + FyN - FyS) * c.inv_h - ac2 * (s10 * c.cStd);
         T F1 = T(1), F2 = uC;
         if (kFrozen) {
-          T zeta = (T)ghost(m, ny, a.bcy) * c.h + off;
+          T zeta = (T)ghost_near(m, ny, a.bcy) * c.h + off;
           F1 = T(1) - c.omk * zeta * c.inv_lT;
           F2 = uC + zeta * c.inv_lT;
         }
@@ -202,30 +218,21 @@ __global__ __launch_bounds__(256) void step2d_kernel(Step2DArgs<T> a) {
           if (m == 0) aAS = aAC;
           if (m == ny) aAC = aAS;
         }
-        if (out_lane && m >= y0 && m < ye) {
-          a.psi_out[(size_t)m * (size_t)nx + (size_t)x] = pC + c.dt * rate;
-          if (kReduce) {
-            double fc = (double)fC;
-            acc.fs += 0.5 * (1.0 + fc);
-            acc.bad += (M::finite(pC) && M::finite(uC)) ? 0u : 1u;
-            if (m <= ny - 2 && fC >= T(0) && fN < T(0)) {
-              double fn = (double)fN;
-              double yy = ((double)m + fc / (fc - fn)) * a.hd;
-              long long id = (long long)m * nx + x;
-              if (yy > acc.y || (yy == acc.y && id < acc.idx)) {
-                acc.y = yy;
-                acc.idx = id;
-              }
-            }
+        if (P >= 3 && m < ye) {
+          if (out_lane) a.psi_out[(size_t)m * (size_t)nx + (size_t)x] = pC + c.dt * rate;
+          if (kReduce && out_lane && m <= ny - 2 && fC >= T(0) && fN < T(0)) {
+            // interface cell: phi = 0 crossing height, FP64 (frame decision)
+            double fc = (double)fC, fn = (double)fN;
+            over |= ((double)m + fc / (fc - fn)) * a.hd >= ythr;
           }
         }
       }
       FyS = FyN;
 
-      const int q = r - 2;
-      if (q >= y0 - 1) {
-        // ---------------- divergences on the row pair (q, q+1) = (S, C)
+      if constexpr (P >= 3) {
+        // ---------------- divergences on the row pair (q, q+1) = (S, C), q = r-2
         // field D: alpha = 1 - phi, beta = U;  field A: alpha = alpha_A, beta = psi
+        const int q = r - 2;
         T aq = T(1) - fS, aq1 = T(1) - fC;
         T aE = from_right(aq), aNE = from_right(aq1);
         T PD = (aq + aE + aq1 + aNE) * T(0.25);
@@ -242,37 +249,43 @@ __global__ __launch_bounds__(256) void step2d_kernel(Step2DArgs<T> a) {
         T fNA = (aAS + aAC + PA + PAW) * (pC - pS);
         T d1A = PA * (pCE - pS), d2A = PAW * (pCW - pS);
 
-        if (q >= y0) {
+        if constexpr (P == 4) {
           T fWD = -from_left(fED), fWA = -from_left(fEA);
           T swD = -from_left(c1D), seD = -from_right(c2D);
           T swA = -from_left(c1A), seA = -from_right(c2A);
           T divD = c.cD1 * (fED + fWD + fND - cND) + c.cD2 * (d1D + d2D + swD + seD);
           T divA = c.cD1 * (fEA + fWA + fNA - cNA) + c.cD2 * (d1A + d2A + swA + seA);
           T rU = (c.D * divD + divA + sq2 * aAS) * M::rcp(T(1) + c.k - c.omk * fS);
-          if (out_lane && q < ye) a.U_out[(size_t)q * (size_t)nx + (size_t)x] = uS + c.dt * rU;
+          if (out_lane) a.U_out[(size_t)q * (size_t)nx + (size_t)x] = uS + c.dt * rU;
         }
         cND = fND; c1D = d1D; c2D = d2D; cPD = PD;
         cNA = fNA; c1A = d1A; c2A = d2A; cPA = PA;
       }
-    }
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    using I4 = std::integral_constant<int, 4>;
+    iter(I0{}, y0 - 2);
+    iter(I1{}, y0 - 1);
+    iter(I2{}, y0);
+    iter(I3{}, y0 + 1);
+    for (int r = y0 + 2; r <= ye + 1; ++r) iter(I4{}, r);
+    if (kReduce) over_any = __any(over);
   }
 
   if (kReduce) {
-    __shared__ TipAcc lds[16];
-    const Step2DArgs<T> *ap = &a;
-    tip_block_and_grid(acc, a.red.partials, a.red.counter, lds, [ap](const TipAcc &t) {
-      TipResult *res = ap->red.result;
-      res->y = t.y;
-      res->idx = t.idx;
-      res->fs_sum = t.fs;
-      res->bad = t.bad;
-      res->found = t.y > -__builtin_inf() ? 1 : 0;
-      if (ap->frame) {
-        int sh = (res->found && t.y >= (double)ap->shift_row * ap->hd) ? 1 : 0;
-        ap->frame_out->shift = ap->frame_in->shift + sh;
-        ap->frame_out->pending = sh;
-      }
-    });
+    // moving frame: publish the shift count of this level, flag the next
+    // level for a one-row shift if any crossing reached the shift row, and
+    // clear the record the next step will write into
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      const FrameState fi = *a.frame_in;
+      a.frame_out->base = fi.base + fi.pending;
+      a.frame_clear->pending = 0;
+    }
+    if (over_any && lane == 0)
+      __hip_atomic_fetch_or(&a.frame_out->pending, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 

@@ -33,7 +33,7 @@ PF_SCHEME_ISO, PF_SCHEME_STD, PF_SCHEME_WEIGHTS = 0, 1, 2
 
 EXPORTED = ("pf_version", "pf_last_error", "pf_stable_dt", "pf_workspace_bytes", "pf_create",
             "pf_step", "pf_synchronize", "pf_read_fields", "pf_tip_state", "pf_device_fields",
-            "pf_frame_state", "pf_destroy")
+            "pf_frame_state", "pf_tune", "pf_destroy")
 
 
 class pf_params(C.Structure):
@@ -91,10 +91,11 @@ def load(path: str = LIB_PATH):
     lib.pf_tip_state.argtypes = [C.c_void_p, P(pf_tip)]
     lib.pf_device_fields.argtypes = [C.c_void_p, P(C.c_void_p), P(C.c_void_p)]
     lib.pf_frame_state.argtypes = [C.c_void_p, P(C.c_int64), P(C.c_int32)]
+    lib.pf_tune.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
     lib.pf_destroy.argtypes = [C.c_void_p]
     lib.pf_destroy.restype = None
     for name in ("pf_create", "pf_step", "pf_synchronize", "pf_read_fields", "pf_tip_state",
-                 "pf_device_fields", "pf_frame_state"):
+                 "pf_device_fields", "pf_frame_state", "pf_tune"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -203,6 +204,9 @@ class Solver:
         a, b = C.c_void_p(), C.c_void_p()
         _check(load().pf_device_fields(self.handle, C.byref(a), C.byref(b)))
         return a.value, b.value
+
+    def tune(self, rows_per_segment: int, z_tile: int = 1):
+        _check(load().pf_tune(self.handle, int(rows_per_segment), int(z_tile)))
 
     def close(self):
         if getattr(self, "handle", None) is not None:

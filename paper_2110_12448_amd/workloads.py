@@ -222,7 +222,8 @@ def config_directional_2d(nx: int = 1024, ny: int = 2048, seed: int = 2, **kw) -
     """Directional solidification in a moving frame: nx x ny, misorientation
     uniform in [0, 45] deg, frame shift at row ny/2."""
     kw.setdefault("alpha0_deg", misorientation(seed))
-    return problem(2, (nx, ny), frame=1, seed=seed, **kw)
+    kw.setdefault("frame", 1)
+    return problem(2, (nx, ny), seed=seed, **kw)
 
 
 def config_polycrystal_3d(n: int = 256, n_grains: int = 8, seed: int = 3, ny: Optional[int] = None,
