@@ -41,7 +41,11 @@ int default_seg2d(int nx, int ny) {
   return (int)(seg < 8 ? 8 : (seg > 32 ? 32 : seg));
 }
 constexpr int kDefaultSeg3D = 16;
-constexpr int kDefaultZTile3D = 4;
+// z rows per 3D workgroup: 6 (8 waves, 53 KB of LDS) in FP32, 2 in FP64 so
+// that the five-row LDS rings stay within 64 KB
+constexpr int kDefaultZTile3D_F32 = 6;
+constexpr int kDefaultZTile3D_F64 = 2;
+constexpr size_t kMaxLds3D = 65536;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -441,7 +445,7 @@ int pf_create(const pf_params *p, const pf_init *init, void *workspace, size_t w
   s->fcur = 0;
   s->step = 0;
   s->seg = p->dim == 2 ? default_seg2d(p->nx, p->ny) : kDefaultSeg3D;
-  s->ztile = kDefaultZTile3D;
+  s->ztile = p->precision == PF_F64 ? kDefaultZTile3D_F64 : kDefaultZTile3D_F32;
   s->have_prev = false;
   if (workspace) {
     if (workspace_bytes < L.total || (reinterpret_cast<uintptr_t>(workspace) & 255u)) {
@@ -570,6 +574,9 @@ int pf_tune(pf_solver *s, int32_t rows_per_segment, int32_t z_tile) {
     return fail(PF_ERR_ARG, "rows_per_segment must lie in [4, 256]");
   if (s->p.dim == 3 && (z_tile < 1 || z_tile > 8))
     return fail(PF_ERR_ARG, "z_tile must lie in [1, 8]");
+  if (s->p.dim == 3 &&
+      step3d_lds_bytes(z_tile, s->p.precision == PF_F64 ? 8 : 4) > kMaxLds3D)
+    return fail(PF_ERR_ARG, "z_tile too large for the LDS of one workgroup at this precision");
   s->seg = rows_per_segment;
   if (s->p.dim == 3) s->ztile = z_tile;
   return PF_OK;

@@ -110,6 +110,7 @@ struct Geom3D {
   int wout, nstrips, ztile, nzt, nsegs, seg, blocks, threads;
 };
 Geom3D geom3d(int nx, int ny, int nz, int seg, int ztile);
+size_t step3d_lds_bytes(int ztile, size_t elem);
 
 size_t tip_acc_bytes();
 int reduce_blocks(int nx, int ny, int nz);
