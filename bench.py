@@ -11,6 +11,10 @@ whole timed region.
 Prints one JSON line (cell-updates/s) with a roofline entry for the step
 kernel and the FP64 CPU oracle timed on a bounded sample of the same
 workload.
+
+--workload polycrystal3d runs the 256^3 FP32 polycrystal (8 Voronoi grains,
+S-bar_{1,2,0}) instead; --copy-calibration runs a plain device copy of known
+size (the reference for the HBM byte counters).
 """
 import argparse
 import hashlib
@@ -31,6 +35,11 @@ PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector (published)
 ALG_FLOPS_2D = 237
 # compulsory bytes per cell-update: read psi, U; write psi, U (FP32)
 ALG_BYTES_2D_F32 = 16
+# FP32 operations per cell-update of the 3D step as written in step3d.hip
+# (same counting rules; derivation in the design doc)
+ALG_FLOPS_3D = 1000
+# read psi, U, the int8 grain; write psi, U
+ALG_BYTES_3D_F32 = 17
 
 
 def src_digest(paths):
@@ -41,22 +50,56 @@ def src_digest(paths):
     return h.hexdigest()[:16]
 
 
-KERNEL_SOURCES = ["paper_2110_12448_amd/csrc/step2d.hip", "paper_2110_12448_amd/csrc/pf_device.hpp"]
+WORKLOADS = {
+    "directional2d": dict(
+        sources=["paper_2110_12448_amd/csrc/step2d.hip", "paper_2110_12448_amd/csrc/pf_device.hpp"],
+        counters="profiles/step2d_directional_1024x2048_counters.json",
+        kernel="step2d_kernel<float,frozen,frame>", flops=ALG_FLOPS_2D, bytes=ALG_BYTES_2D_F32,
+        steps=20000, warmup=500,
+        text="2D directional solidification, moving frame, 1024x2048, S-bar_{2,1}, FP32 "
+             "fields, FP64 tip/fraction reductions"),
+    "polycrystal3d": dict(
+        sources=["paper_2110_12448_amd/csrc/step3d.hip", "paper_2110_12448_amd/csrc/pf_device.hpp"],
+        counters="profiles/step3d_polycrystal_256cubed_counters.json",
+        kernel="step3d_kernel<float,frozen,multigrain>", flops=ALG_FLOPS_3D, bytes=ALG_BYTES_3D_F32,
+        steps=300, warmup=20,
+        text="3D polycrystal, 256^3, 8 Voronoi grains with uniform random cubic orientations, "
+             "S-bar_{1,2,0}, FP32 fields"),
+}
 
 
-def load_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "step2d_directional_1024x2048_counters.json")
+def load_counters(wk):
+    """The committed rocprofv3 counter summary of the workload's step kernel,
+    if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, wk["counters"])
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    if d.get("source_digest") != src_digest(KERNEL_SOURCES):
+    if d.get("source_digest") != src_digest(wk["sources"]):
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d
 
 
-def cpu_baseline(pr, target_s=12.0, max_steps=40):
+def copy_calibration(nbytes=1 << 30, reps=20):
+    """Device-to-device copy of nbytes, reps times (the reference kernel for the
+    FETCH_SIZE / WRITE_SIZE counters)."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps,
+                      "ms_per_copy": ms, "GBs_read_plus_write": 2 * nbytes / ms / 1e6}))
+
+
+def cpu_baseline(pr, target_s=12.0, max_steps=40, label="1024x2048 directional"):
     import numpy as np
     import oracle
     p = oracle.Params.from_problem(pr)
@@ -68,21 +111,33 @@ def cpu_baseline(pr, target_s=12.0, max_steps=40):
         psi, U, st = oracle.step(p, psi, U, g, 1, st)
         steps += 1
     dt = time.perf_counter() - t0
-    cells = pr["nx"] * pr["ny"]
+    cells = pr["nx"] * pr["ny"] * pr["nz"]
     return {"value": cells * steps / dt, "unit": "cell-updates/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": "FP64 oracle, first %d steps of the same 1024x2048 directional solve "
-                      "(%.1f s)" % (steps, dt)}, steps, psi, U, st
+            "sample": "FP64 oracle, first %d steps of the same %s solve "
+                      "(%.1f s)" % (steps, label, dt)}, steps, psi, U, st
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=500)
-    ap.add_argument("--launch-sample", type=int, default=400)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--launch-sample", type=int, default=None)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="directional2d")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    wk = WORKLOADS[args.workload]
+    if args.steps is None:
+        args.steps = wk["steps"]
+    if args.warmup is None:
+        args.warmup = wk["warmup"]
+    if args.launch_sample is None:
+        args.launch_sample = min(400, args.steps)
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -95,13 +150,16 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    pr = wl.config_directional_2d()
-    cells = pr["nx"] * pr["ny"]
+    if args.workload == "directional2d":
+        pr = wl.config_directional_2d()
+    else:
+        pr = wl.config_polycrystal_3d()
+    cells = pr["nx"] * pr["ny"] * pr["nz"]
     s = pfiso.Solver(pr, precision=pfiso.PF_F32, device="cuda:0")
     st = s.stream
-    print("bench: %dx%d FP32 directional, alpha0=%.2f deg, warmup %d" %
-          (pr["nx"], pr["ny"], math.degrees(math.atan2(pr["rot"][0][1][0], pr["rot"][0][0][0])),
-           args.warmup), file=sys.stderr, flush=True)
+    print("bench: %s %dx%dx%d FP32, warmup %d, steps %d" %
+          (args.workload, pr["nx"], pr["ny"], pr["nz"], args.warmup, args.steps),
+          file=sys.stderr, flush=True)
     s.step(args.warmup)
     s.tip_state()
     torch.cuda.synchronize()
@@ -129,21 +187,28 @@ def main():
     tip = s.tip_state()
     s.close()
 
-    achieved_tflops = ALG_FLOPS_2D * cells / (kern_ms / 1e3) / 1e12
-    achieved_gbs = ALG_BYTES_2D_F32 * cells / (kern_ms / 1e3) / 1e9
-    traffic = load_traffic()
+    achieved_tflops = wk["flops"] * cells / (kern_ms / 1e3) / 1e12
+    achieved_gbs = wk["bytes"] * cells / (kern_ms / 1e3) / 1e9
+    ctr = load_counters(wk)
+    traffic = None if ctr is None else ctr["hbm_bytes_per_launch"]
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
                 "traffic": traffic,
-                "kernel": "step2d_kernel<float,frozen,reduce>", "kernel_ms": round(kern_ms, 5),
+                "kernel": wk["kernel"], "kernel_ms": round(kern_ms, 5),
                 "hbm_algorithmic_GBs": round(achieved_gbs, 1),
                 "hbm_frac": round(achieved_gbs / PEAK_HBM_GBS, 4),
-                "flops_per_cell": ALG_FLOPS_2D, "bytes_per_cell": ALG_BYTES_2D_F32}
+                "flops_per_cell": wk["flops"], "bytes_per_cell": wk["bytes"],
+                "valu_issue_frac": None if ctr is None else round(ctr["valu_issue_utilisation"], 3),
+                "counters_kernel_ns": None if ctr is None else ctr["avg_duration_ns"]}
 
     cpu = None
     err = None
     if not args.no_cpu:
-        cpu, nst, opsi, oU, ost = cpu_baseline(pr)
+        if args.workload == "directional2d":
+            cpu, nst, opsi, oU, ost = cpu_baseline(pr)
+        else:
+            cpu, nst, opsi, oU, ost = cpu_baseline(pr, target_s=15.0, max_steps=3,
+                                                   label="256^3 polycrystal")
         # the same number of steps on the GPU, compared with the oracle state
         s2 = pfiso.Solver(pr, precision=pfiso.PF_F32, device="cuda:0")
         s2.step(nst)
@@ -166,9 +231,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "2D directional solidification, moving frame, 1024x2048, "
-                               "S-bar_{2,1}, FP32 fields, FP64 tip/fraction reductions",
-                   "nx": pr["nx"], "ny": pr["ny"], "h": pr["h"], "dt": pr["dt"],
+        "config": {"workload": wk["text"],
+                   "nx": pr["nx"], "ny": pr["ny"], "nz": pr["nz"], "h": pr["h"], "dt": pr["dt"],
                    "k": pr["k"], "eps4": pr["eps4"], "D": pr["D"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
