@@ -68,6 +68,57 @@ WORKLOADS = {
 }
 
 
+def bench_batched(args):
+    """64 uneven 2D solves (sides 256..1024) stepped by one launch per step
+    (HIP graph of 10 launches), against the same solves stepped one at a time
+    in FP32 and in FP64."""
+    import torch
+    from paper_2110_12448_amd import pfiso
+    from paper_2110_12448_amd import workloads as wl
+    prs = wl.config_batched_2d()
+    cells = sum(p["nx"] * p["ny"] for p in prs)
+    steps = args.steps or 500
+    warm = args.warmup if args.warmup is not None else 20
+
+    def timed(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    ss = [pfiso.Solver(p, precision=pfiso.PF_F32) for p in prs]
+    b = pfiso.Batch(ss, graph_steps=10)
+    b.step(warm)
+    t = timed(lambda: b.step(steps))
+    batched = cells * steps / t
+    b.close()
+    solo_steps = max(10, steps // 5)
+    t32 = timed(lambda: [s.step(solo_steps) for s in ss])
+    for s in ss:
+        s.close()
+    ss = [pfiso.Solver(p, precision=pfiso.PF_F64) for p in prs]
+    for s in ss:
+        s.step(2)
+    t64 = timed(lambda: [s.step(solo_steps // 2) for s in ss])
+    for s in ss:
+        s.close()
+    out = {"metric": "phi+U cell-updates/s (batched)", "value": batched,
+           "unit": "cell-updates/s", "n_gpus": 1, "steps": steps, "warmup": warm,
+           "ms_per_step": t / steps * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "64 independent 2D solves, sides from {256,384,512,768,1024}, "
+                                  "misorientation uniform in [0,45] deg, S-bar_{2,1}, one launch "
+                                  "per step replayed from a HIP graph", "solves": len(prs),
+                      "cells": cells},
+           "one_at_a_time_f32": cells * solo_steps / t32,
+           "one_at_a_time_f64": cells * (solo_steps // 2) / t64}
+    print(json.dumps(out))
+
+
 def load_counters(wk):
     """The committed rocprofv3 counter summary of the workload's step kernel,
     if it was taken on the current kernel source; else None."""
@@ -124,12 +175,19 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--launch-sample", type=int, default=None)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="directional2d")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batched2d"],
+                    default="directional2d")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.workload == "batched2d":
+        if args.gpus != 1:
+            print("bench.py runs on one GPU only", file=sys.stderr)
+            sys.exit(2)
+        bench_batched(args)
         return
     wk = WORKLOADS[args.workload]
     if args.steps is None:

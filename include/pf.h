@@ -165,6 +165,32 @@ int pf_tune(pf_solver *s, int32_t rows_per_segment, int32_t z_tile);
 /* Release the solver (and its workspace if the library allocated it). */
 void pf_destroy(pf_solver *s);
 
+/* ------------------------------------------------------------- batching
+ * Many 2D solves advanced together: every step of every solve in ONE kernel
+ * launch (each workgroup runs one tile of one solve), optionally replayed from
+ * a captured HIP graph.  The solves keep their own workspaces and stay
+ * usable through the calls above (read-back, tip state, single steps); a
+ * batch only needs its solvers to be alive, 2D, of one precision, of one kind
+ * (all frozen or all isothermal, all with or without the moving frame, all
+ * single- or all multi-grain) and bound to one stream.  Results are bitwise
+ * those of stepping each solve on its own with the same launch geometry. */
+typedef struct pf_batch pf_batch;
+
+/* Build a batch over n solvers (the caller keeps the solvers). */
+int pf_batch_create(pf_solver *const *solvers, int32_t n, pf_batch **out);
+
+/* Enqueue nsteps steps of every solve; no host synchronisation (a solver
+ * stepped on its own since the last call is picked up, at the cost of one
+ * synchronisation). */
+int pf_batch_step(pf_batch *b, int64_t nsteps);
+
+/* Capture steps_per_graph launches (a multiple of 2; of 6 with the moving
+ * frame) into a HIP graph replayed by pf_batch_step; 0 launches directly. */
+int pf_batch_use_graph(pf_batch *b, int32_t steps_per_graph);
+
+/* Release the batch (not its solvers). */
+void pf_batch_destroy(pf_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -40,10 +40,10 @@ int default_seg2d(int nx, int ny) {
   long long seg = strips * ny / 4608;
   return (int)(seg < 8 ? 8 : (seg > 32 ? 32 : seg));
 }
-constexpr int kDefaultSeg3D = 16;
-// z rows per 3D workgroup: 6 (8 waves, 53 KB of LDS) in FP32, 2 in FP64 so
-// that the five-row LDS rings stay within 64 KB
-constexpr int kDefaultZTile3D_F32 = 6;
+constexpr int kDefaultSeg3D = 32;
+// z rows per 3D workgroup: 8 (10 waves, 62 KB of LDS) in FP32, 2 in FP64 so
+// that the five-row LDS rings stay within 64 KB (tile sweep on 256^3)
+constexpr int kDefaultZTile3D_F32 = 8;
 constexpr int kDefaultZTile3D_F64 = 2;
 constexpr size_t kMaxLds3D = 65536;
 
@@ -270,6 +270,23 @@ int upload(pf_solver *s, const pf_init *init) {
   return PF_OK;
 }
 
+// Argument block of the 2D step of solver s (pointers set per launch).
+template <typename T>
+Geom2D fill2d(pf_solver *s, Step2DArgs<T> &a) {
+  const pf_params &p = s->p;
+  memset(&a, 0, sizeof(a));
+  Geom2D g = geom2d(p.nx, p.ny, s->seg);
+  a.grain = p.n_grains > 1 ? reinterpret_cast<const int8_t *>(s->ws + s->L.grain) : nullptr;
+  a.rot = field<T>(s, s->L.rot);
+  a.r00 = (T)s->rot[0]; a.r01 = (T)s->rot[1]; a.r10 = (T)s->rot[3]; a.r11 = (T)s->rot[4];
+  a.nx = p.nx; a.ny = p.ny; a.bcx = p.bc[0]; a.bcy = p.bc[1];
+  a.wout = g.wout; a.nstrips = g.nstrips; a.nsegs = g.nsegs; a.seg = g.seg;
+  a.c = coef_of<T>(s);
+  a.hd = p.h; a.y0 = p.y0; a.Vp = p.Vp; a.dtd = s->dt;
+  a.frame = p.frame; a.shift_row = p.shift_row;
+  return g;
+}
+
 template <typename T>
 int step_impl(pf_solver *s, long long nsteps) {
   const pf_params &p = s->p;
@@ -280,16 +297,8 @@ int step_impl(pf_solver *s, long long nsteps) {
   auto frec = [&](int i) { return reinterpret_cast<FrameState *>(s->ws + s->L.frame[i % 3]); };
   if (p.dim == 2) {
     Step2DArgs<T> a;
-    memset(&a, 0, sizeof(a));
-    Geom2D g = geom2d(p.nx, p.ny, s->seg);
-    a.grain = multi ? reinterpret_cast<const int8_t *>(s->ws + s->L.grain) : nullptr;
-    a.rot = field<T>(s, s->L.rot);
-    a.r00 = (T)s->rot[0]; a.r01 = (T)s->rot[1]; a.r10 = (T)s->rot[3]; a.r11 = (T)s->rot[4];
-    a.nx = p.nx; a.ny = p.ny; a.bcx = p.bc[0]; a.bcy = p.bc[1];
-    a.wout = g.wout; a.nstrips = g.nstrips; a.nsegs = g.nsegs; a.seg = g.seg;
-    a.c = c;
-    a.hd = p.h; a.y0 = p.y0; a.Vp = p.Vp; a.dtd = s->dt;
-    a.frame = p.frame; a.shift_row = p.shift_row;
+    Geom2D g = fill2d<T>(s, a);
+    (void)c;
     for (long long i = 0; i < nsteps; ++i) {
       a.psi_in = field<T>(s, s->L.psi[s->cur]);
       a.U_in = field<T>(s, s->L.U[s->cur]);
@@ -382,7 +391,200 @@ int read_impl(pf_solver *s, double *phi, double *U, double *psi) {
 
 }  // namespace
 
+struct pf_batch {
+  std::vector<pf_solver *> s;
+  int precision;
+  bool frozen, frame, multi;
+  hipStream_t stream;
+  void *table;  // device BatchSolve2D<T>[n]
+  int2 *map;    // device workgroup map
+  int blocks;
+  std::vector<long long> expect;  // solver steps the device table assumes
+  std::vector<int> seg;           // segment lengths the table was built with
+  int graph_steps;
+  hipStream_t cap;
+  hipGraph_t graph;
+  hipGraphExec_t gexec;
+};
+
+namespace {
+
+int xcd_remap_host(int b, int nb) {
+  const int X = 8;
+  int q = nb / X, r = nb % X, x = b % X;
+  return x * q + (x < r ? x : r) + b / X;
+}
+
+// (Re)build the device table and workgroup map from the solvers' state.
+template <typename T>
+int batch_build(pf_batch *b) {
+  const int n = (int)b->s.size();
+  std::vector<BatchSolve2D<T>> tab(n);
+  std::vector<int2> list;
+  for (int i = 0; i < n; ++i) {
+    pf_solver *s = b->s[i];
+    BatchSolve2D<T> &e = tab[i];
+    memset(&e, 0, sizeof(e));
+    Geom2D g = fill2d<T>(s, e.a);
+    for (int k = 0; k < 2; ++k) {
+      e.psi[k] = field<T>(s, s->L.psi[k]);
+      e.U[k] = field<T>(s, s->L.U[k]);
+    }
+    for (int k = 0; k < 3; ++k) e.frames[k] = reinterpret_cast<FrameState *>(s->ws + s->L.frame[k]);
+    e.n0 = s->step;
+    e.par0 = s->cur;
+    e.f0 = s->fcur;
+    for (int lb = 0; lb < g.blocks; ++lb) list.push_back(int2{i, lb});
+    b->expect[i] = s->step;
+    b->seg[i] = s->seg;
+  }
+  const int total = (int)list.size();
+  std::vector<int2> map(total);
+  for (int k = 0; k < total; ++k) map[k] = list[xcd_remap_host(k, total)];
+  PF_HIP(hipStreamSynchronize(b->stream));
+  if (b->table) (void)hipFree(b->table);
+  if (b->map) (void)hipFree(b->map);
+  b->table = nullptr;
+  b->map = nullptr;
+  PF_HIP(hipMalloc(&b->table, sizeof(BatchSolve2D<T>) * n));
+  PF_HIP(hipMalloc((void **)&b->map, sizeof(int2) * total));
+  PF_HIP(hipMemcpy(b->table, tab.data(), sizeof(BatchSolve2D<T>) * n, hipMemcpyHostToDevice));
+  PF_HIP(hipMemcpy(b->map, map.data(), sizeof(int2) * total, hipMemcpyHostToDevice));
+  b->blocks = total;
+  return PF_OK;
+}
+
+void batch_drop_graph(pf_batch *b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+}
+
+template <typename T>
+int batch_capture(pf_batch *b) {
+  batch_drop_graph(b);
+  if (b->graph_steps <= 0) return PF_OK;
+  auto *tab = reinterpret_cast<BatchSolve2D<T> *>(b->table);
+  PF_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
+  for (int k = 0; k < b->graph_steps; ++k)
+    (void)launch_batch2d<T>(tab, b->map, b->blocks, k, b->frozen, b->frame, b->multi, b->cap);
+  (void)launch_batch2d_advance<T>(tab, (int)b->s.size(), b->graph_steps, b->frame, b->cap);
+  PF_HIP(hipStreamEndCapture(b->cap, &b->graph));
+  PF_HIP(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+  return PF_OK;
+}
+
+template <typename T>
+int batch_step(pf_batch *b, long long nsteps) {
+  bool stale = false;
+  for (size_t i = 0; i < b->s.size(); ++i)
+    if (b->s[i]->step != b->expect[i] || b->s[i]->seg != b->seg[i]) stale = true;
+  if (stale) {
+    int rc = batch_build<T>(b);
+    if (rc != PF_OK) return rc;
+    rc = batch_capture<T>(b);
+    if (rc != PF_OK) return rc;
+  }
+  auto *tab = reinterpret_cast<BatchSolve2D<T> *>(b->table);
+  long long done = 0;
+  if (b->gexec) {
+    for (; done + b->graph_steps <= nsteps; done += b->graph_steps)
+      PF_HIP(hipGraphLaunch(b->gexec, b->stream));
+  }
+  const int rem = (int)(nsteps - done);
+  if (rem > 0) {
+    for (int k = 0; k < rem; ++k)
+      PF_HIP(launch_batch2d<T>(tab, b->map, b->blocks, k, b->frozen, b->frame, b->multi,
+                               b->stream));
+    PF_HIP(launch_batch2d_advance<T>(tab, (int)b->s.size(), rem, b->frame, b->stream));
+  }
+  for (size_t i = 0; i < b->s.size(); ++i) {
+    pf_solver *s = b->s[i];
+    s->step += nsteps;
+    s->cur = (int)((s->cur + nsteps) & 1);
+    if (b->frame) s->fcur = (int)((s->fcur + nsteps) % 3);
+    b->expect[i] = s->step;
+  }
+  return PF_OK;
+}
+
+}  // namespace
+
 extern "C" {
+
+int pf_batch_create(pf_solver *const *solvers, int32_t n, pf_batch **out) {
+  if (!solvers || n < 1 || !out) return fail(PF_ERR_ARG, "need n >= 1 solvers and an out pointer");
+  for (int i = 0; i < n; ++i)
+    if (!solvers[i]) return fail(PF_ERR_ARG, "solver is NULL");
+  const pf_solver *s0 = solvers[0];
+  for (int i = 0; i < n; ++i) {
+    const pf_solver *s = solvers[i];
+    if (s->p.dim != 2) return fail(PF_ERR_ARG, "batched stepping is 2D only");
+    if (s->p.precision != s0->p.precision) return fail(PF_ERR_ARG, "mixed precisions in a batch");
+    if ((s->p.lT > 0.0) != (s0->p.lT > 0.0) || (s->p.frame != 0) != (s0->p.frame != 0) ||
+        (s->p.n_grains > 1) != (s0->p.n_grains > 1))
+      return fail(PF_ERR_ARG, "a batch needs one kind: all frozen or all isothermal, all with or "
+                              "without frame, all single- or all multi-grain");
+    if (s->stream != s0->stream) return fail(PF_ERR_ARG, "solvers of a batch share one stream");
+    for (int j = 0; j < i; ++j)
+      if (solvers[j] == s) return fail(PF_ERR_ARG, "a solver appears twice in the batch");
+  }
+  pf_batch *b = new (std::nothrow) pf_batch();
+  if (!b) return fail(PF_ERR_OOM, "host allocation failed");
+  b->s.assign(solvers, solvers + n);
+  b->precision = s0->p.precision;
+  b->frozen = s0->p.lT > 0.0;
+  b->frame = s0->p.frame != 0;
+  b->multi = s0->p.n_grains > 1;
+  b->stream = s0->stream;
+  b->table = nullptr;
+  b->map = nullptr;
+  b->expect.assign(n, -1);
+  b->seg.assign(n, -1);
+  b->graph_steps = 0;
+  b->graph = nullptr;
+  b->gexec = nullptr;
+  if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+    delete b;
+    return fail(PF_ERR_DEVICE, "capture stream creation failed");
+  }
+  int rc = b->precision == PF_F64 ? batch_build<double>(b) : batch_build<float>(b);
+  if (rc != PF_OK) {
+    pf_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return PF_OK;
+}
+
+int pf_batch_step(pf_batch *b, int64_t nsteps) {
+  if (!b) return fail(PF_ERR_ARG, "batch is NULL");
+  if (nsteps < 0) return fail(PF_ERR_ARG, "nsteps must be >= 0");
+  return b->precision == PF_F64 ? batch_step<double>(b, nsteps) : batch_step<float>(b, nsteps);
+}
+
+int pf_batch_use_graph(pf_batch *b, int32_t steps_per_graph) {
+  if (!b) return fail(PF_ERR_ARG, "batch is NULL");
+  if (steps_per_graph < 0) return fail(PF_ERR_ARG, "steps_per_graph must be >= 0");
+  if (steps_per_graph > 0 && steps_per_graph % (b->frame ? 6 : 2) != 0)
+    return fail(PF_ERR_ARG, "steps_per_graph must be a multiple of 2 (6 with the moving frame)");
+  b->graph_steps = steps_per_graph;
+  PF_HIP(hipStreamSynchronize(b->stream));
+  int rc = b->precision == PF_F64 ? batch_build<double>(b) : batch_build<float>(b);
+  if (rc != PF_OK) return rc;
+  return b->precision == PF_F64 ? batch_capture<double>(b) : batch_capture<float>(b);
+}
+
+void pf_batch_destroy(pf_batch *b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  batch_drop_graph(b);
+  if (b->table) (void)hipFree(b->table);
+  if (b->map) (void)hipFree(b->map);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  delete b;
+}
 
 int pf_version(void) { return PF_VERSION; }
 

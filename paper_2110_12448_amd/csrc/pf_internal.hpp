@@ -73,6 +73,19 @@ struct Step2DArgs {
   FrameState *frame_out, *frame_clear;
 };
 
+// One solve of a batched 2D launch: its argument block plus both buffer
+// pairs, its three frame records and the epoch origin (level n0, buffer
+// parity and frame-record index at launch k = 0).
+template <typename T>
+struct BatchSolve2D {
+  Step2DArgs<T> a;
+  T *psi[2];
+  T *U[2];
+  FrameState *frames[3];
+  long long n0;
+  int par0, f0;
+};
+
 template <typename T>
 struct Step3DArgs {
   const T *psi_in, *U_in;
@@ -123,5 +136,11 @@ hipError_t launch_step3d(const Step3DArgs<T> &a, const Geom3D &g, bool frozen, b
                          bool multi, hipStream_t st);
 template <typename T>
 hipError_t launch_reduce(const ReduceArgs<T> &a, hipStream_t st);
+template <typename T>
+hipError_t launch_batch2d(const BatchSolve2D<T> *table, const int2 *map, int blocks, int k,
+                          bool frozen, bool reduce, bool multi, hipStream_t st);
+template <typename T>
+hipError_t launch_batch2d_advance(BatchSolve2D<T> *table, int n, int steps, bool frame,
+                                  hipStream_t st);
 
 }  // namespace pf

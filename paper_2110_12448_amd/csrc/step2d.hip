@@ -83,12 +83,12 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return x * q + (x < r ? x : r) + b / X;
 }
 
+// One logical workgroup `lb` (4 waves) of the step of one solve `a`.
 template <typename T, bool kFrozen, bool kReduce, bool kMulti>
-__global__ __launch_bounds__(256) void step2d_kernel(Step2DArgs<T> a) {
+__device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb) {
   using M = Math<T>;
   const Coef<T> &c = a.c;
   const int lane = threadIdx.x & 63;
-  const int lb = xcd_remap((int)blockIdx.x, (int)gridDim.x);
   // wave-uniform: keeps strip, segment and row counters in scalar registers
   const int wave = lb * 4 + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int nx = a.nx, ny = a.ny;
@@ -279,13 +279,54 @@ __global__ __launch_bounds__(256) void step2d_kernel(Step2DArgs<T> a) {
     // moving frame: publish the shift count of this level, flag the next
     // level for a one-row shift if any crossing reached the shift row, and
     // clear the record the next step will write into
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (lb == 0 && threadIdx.x == 0) {
       const FrameState fi = *a.frame_in;
       a.frame_out->base = fi.base + fi.pending;
       a.frame_clear->pending = 0;
     }
     if (over_any && lane == 0)
       __hip_atomic_fetch_or(&a.frame_out->pending, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <typename T, bool kFrozen, bool kReduce, bool kMulti>
+__global__ __launch_bounds__(256) void step2d_kernel(Step2DArgs<T> a) {
+  step2d_body<T, kFrozen, kReduce, kMulti>(a, xcd_remap((int)blockIdx.x, (int)gridDim.x));
+}
+
+// Many solves in one launch: workgroup b runs logical workgroup map[b].y of
+// solve map[b].x.  Launch k of an epoch steps every solve from its level
+// n0 + k: buffers and frame records are picked from the epoch's parities.
+template <typename T, bool kFrozen, bool kReduce, bool kMulti>
+__global__ __launch_bounds__(256) void batch2d_kernel(const BatchSolve2D<T> *table,
+                                                      const int2 *map, int k) {
+  const int2 bm = map[blockIdx.x];
+  const BatchSolve2D<T> &e = table[bm.x];
+  Step2DArgs<T> a = e.a;
+  const long long n = e.n0 + k;
+  const int par = (int)((e.par0 + k) & 1);
+  a.psi_in = e.psi[par];
+  a.U_in = e.U[par];
+  a.psi_out = e.psi[par ^ 1];
+  a.U_out = e.U[par ^ 1];
+  a.step = n;
+  if (kReduce) {
+    const int f = (e.f0 + k) % 3;
+    a.frame_in = e.frames[f];
+    a.frame_out = e.frames[(f + 1) % 3];
+    a.frame_clear = e.frames[(f + 2) % 3];
+  }
+  step2d_body<T, kFrozen, kReduce, kMulti>(a, bm.y);
+}
+
+// Advance the epoch origin of every solve by `steps` (end of a captured graph).
+template <typename T>
+__global__ void batch2d_advance(BatchSolve2D<T> *table, int n, int steps, int frame) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    table[i].n0 += steps;
+    table[i].par0 = (table[i].par0 + steps) & 1;
+    if (frame) table[i].f0 = (table[i].f0 + steps) % 3;
   }
 }
 
@@ -318,6 +359,40 @@ hipError_t launch_step2d(const Step2DArgs<T> &a, const Geom2D &g, bool frozen, b
 #undef PF_L2
   return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_batch2d(const BatchSolve2D<T> *table, const int2 *map, int blocks, int k,
+                          bool frozen, bool reduce, bool multi, hipStream_t st) {
+  dim3 grid(blocks), block(256);
+#define PF_LB(F, R, MU) \
+  hipLaunchKernelGGL((batch2d_kernel<T, F, R, MU>), grid, block, 0, st, table, map, k)
+  if (frozen) {
+    if (reduce) { if (multi) PF_LB(true, true, true); else PF_LB(true, true, false); }
+    else { if (multi) PF_LB(true, false, true); else PF_LB(true, false, false); }
+  } else {
+    if (reduce) { if (multi) PF_LB(false, true, true); else PF_LB(false, true, false); }
+    else { if (multi) PF_LB(false, false, true); else PF_LB(false, false, false); }
+  }
+#undef PF_LB
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_batch2d_advance(BatchSolve2D<T> *table, int n, int steps, bool frame,
+                                  hipStream_t st) {
+  hipLaunchKernelGGL((batch2d_advance<T>), dim3((n + 63) / 64), dim3(64), 0, st, table, n, steps,
+                     frame ? 1 : 0);
+  return hipGetLastError();
+}
+
+template hipError_t launch_batch2d<float>(const BatchSolve2D<float> *, const int2 *, int, int,
+                                          bool, bool, bool, hipStream_t);
+template hipError_t launch_batch2d<double>(const BatchSolve2D<double> *, const int2 *, int, int,
+                                           bool, bool, bool, hipStream_t);
+template hipError_t launch_batch2d_advance<float>(BatchSolve2D<float> *, int, int, bool,
+                                                  hipStream_t);
+template hipError_t launch_batch2d_advance<double>(BatchSolve2D<double> *, int, int, bool,
+                                                   hipStream_t);
 
 template hipError_t launch_step2d<float>(const Step2DArgs<float> &, const Geom2D &, bool, bool,
                                          bool, hipStream_t);

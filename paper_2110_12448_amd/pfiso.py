@@ -33,7 +33,8 @@ PF_SCHEME_ISO, PF_SCHEME_STD, PF_SCHEME_WEIGHTS = 0, 1, 2
 
 EXPORTED = ("pf_version", "pf_last_error", "pf_stable_dt", "pf_workspace_bytes", "pf_create",
             "pf_step", "pf_synchronize", "pf_read_fields", "pf_tip_state", "pf_device_fields",
-            "pf_frame_state", "pf_tune", "pf_destroy")
+            "pf_frame_state", "pf_tune", "pf_destroy", "pf_batch_create", "pf_batch_step",
+            "pf_batch_use_graph", "pf_batch_destroy")
 
 
 class pf_params(C.Structure):
@@ -94,8 +95,14 @@ def load(path: str = LIB_PATH):
     lib.pf_tune.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
     lib.pf_destroy.argtypes = [C.c_void_p]
     lib.pf_destroy.restype = None
+    lib.pf_batch_create.argtypes = [P(C.c_void_p), C.c_int32, P(C.c_void_p)]
+    lib.pf_batch_step.argtypes = [C.c_void_p, C.c_int64]
+    lib.pf_batch_use_graph.argtypes = [C.c_void_p, C.c_int32]
+    lib.pf_batch_destroy.argtypes = [C.c_void_p]
+    lib.pf_batch_destroy.restype = None
     for name in ("pf_create", "pf_step", "pf_synchronize", "pf_read_fields", "pf_tip_state",
-                 "pf_device_fields", "pf_frame_state", "pf_tune"):
+                 "pf_device_fields", "pf_frame_state", "pf_tune", "pf_batch_create",
+                 "pf_batch_step", "pf_batch_use_graph"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -211,6 +218,37 @@ class Solver:
     def close(self):
         if getattr(self, "handle", None) is not None:
             load().pf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several 2D solvers advanced by one kernel launch per step (pf_batch_*)."""
+
+    def __init__(self, solvers, graph_steps: int = 0):
+        lib = load()
+        self.solvers = list(solvers)
+        arr = (C.c_void_p * len(self.solvers))(*[s.handle.value for s in self.solvers])
+        h = C.c_void_p()
+        _check(lib.pf_batch_create(arr, len(self.solvers), C.byref(h)))
+        self.handle = h
+        if graph_steps:
+            self.use_graph(graph_steps)
+
+    def use_graph(self, steps_per_graph: int):
+        _check(load().pf_batch_use_graph(self.handle, int(steps_per_graph)))
+
+    def step(self, nsteps: int = 1):
+        _check(load().pf_batch_step(self.handle, int(nsteps)))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            load().pf_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

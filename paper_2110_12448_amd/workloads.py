@@ -237,3 +237,17 @@ def config_polycrystal_3d(n: int = 256, n_grains: int = 8, seed: int = 3, ny: Op
     kw.setdefault("seed_shape", "slab")
     kw.setdefault("seed_radius", 5.0)
     return problem(3, (n, ny, n), rot=rot, grain=grain, seed=seed, **kw)
+
+
+def config_batched_2d(n_solves: int = 64, seed: int = 4, sides=(256, 384, 512, 768, 1024),
+                      **kw) -> list:
+    """n_solves independent square 2D solves, side drawn uniformly from
+    `sides`, misorientation uniform in [0, 45] deg, frozen gradient, disc seed
+    (each solve seeded with its own noise stream)."""
+    u = uniform(seed, 5, 2 * n_solves).reshape(n_solves, 2)
+    out = []
+    for i in range(n_solves):
+        side = int(sides[min(int(u[i, 0] * len(sides)), len(sides) - 1)])
+        out.append(problem(2, (side, side), alpha0_deg=45.0 * float(u[i, 1]),
+                           seed=(seed * 1000 + i) & 0xFFFF, **kw))
+    return out

@@ -1,0 +1,93 @@
+"""Batched 2D stepping (pf_batch_*): every solve of a batch must be bitwise
+identical to the same solve stepped on its own, with and without HIP-graph
+replay, the moving frame, multi-grain maps and interleaved single steps."""
+import numpy as np
+import pytest
+
+from paper_2110_12448_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(64, 64), (97, 130), (200, 61), (128, 256), (31, 40), (256, 128)]
+
+
+def _pf():
+    from paper_2110_12448_amd import pfiso
+    return pfiso
+
+
+def problems(frame=False, multi=False, thermal="isothermal"):
+    out = []
+    for i, (nx, ny) in enumerate(SIZES):
+        a0 = 45.0 * float(wl.uniform(4, 3, len(SIZES))[i])
+        kw = dict(thermal=thermal, alpha0_deg=a0, seed=100 + i, seed_radius=min(nx, ny) / 6.0)
+        if frame:
+            kw.update(frame=1, shift_row=max(2, ny // 5))
+        if multi:
+            rot = np.stack([wl.rotation_2d(a0), wl.rotation_2d(a0 + 20.0)])
+            g = np.zeros((ny, nx), dtype=np.int8)
+            g[:, nx // 2:] = 1
+            kw.update(rot=rot, grain=g)
+        out.append(wl.problem(2, (nx, ny), **kw))
+    return out
+
+
+def solo(pr, prec, nsteps):
+    pf = _pf()
+    s = pf.Solver(pr, precision=prec)
+    s.step(nsteps)
+    phi, U, psi, _ = s.read_fields()
+    fr = s.frame_state()
+    s.close()
+    return psi, U, fr
+
+
+def check_batch(prs, prec, plan, graph=0):
+    """plan: list of ('b', n) batch steps or ('s', i, n) single steps of solve i."""
+    pf = _pf()
+    print("batch of %d solves prec=%d graph=%d plan=%s" % (len(prs), prec, graph, plan), flush=True)
+    ss = [pf.Solver(pr, precision=prec) for pr in prs]
+    b = pf.Batch(ss, graph_steps=graph)
+    total = [0] * len(prs)
+    for item in plan:
+        if item[0] == "b":
+            b.step(item[1])
+            total = [t + item[1] for t in total]
+        else:
+            ss[item[1]].step(item[2])
+            total[item[1]] += item[2]
+            ss[0].tip_state()          # eager work between launches
+    for i, pr in enumerate(prs):
+        phi, U, psi, _ = ss[i].read_fields()
+        fr = ss[i].frame_state()
+        rpsi, rU, rfr = solo(pr, prec, total[i])
+        assert np.array_equal(psi, rpsi) and np.array_equal(U, rU), (i, total[i])
+        assert fr == rfr
+    b.close()
+    for s in ss:
+        s.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_equals_solo(prec):
+    check_batch(problems(), prec, [("b", 25)])
+
+
+def test_batch_frozen_moving_frame():
+    prs = problems(frame=True, thermal="frozen")
+    check_batch(prs, 0, [("b", 30)])
+
+
+def test_batch_multigrain():
+    check_batch(problems(multi=True), 0, [("b", 20)])
+
+
+@pytest.mark.parametrize("graph", [2, 6])
+def test_batch_graph_replays(graph):
+    """Graph replays interleaved with eager work and direct launches."""
+    prs = problems(frame=True, thermal="frozen") if graph == 6 else problems()
+    check_batch(prs, 0, [("b", 13), ("s", 2, 1), ("b", 24), ("s", 0, 3), ("b", 7)], graph=graph)
+
+
+def test_batch_interleaved_single_steps():
+    check_batch(problems(), 1, [("b", 10), ("s", 3, 4), ("b", 10), ("s", 1, 1), ("b", 3)])
