@@ -119,6 +119,29 @@ def bench_batched(args):
     print(json.dumps(out))
 
 
+def bench_serve(args):
+    """Continuous-batching server on a seeded Poisson trace (mean 20 requests/s,
+    80% 2D sides 256..1024, 20% 3D sides 128..192, 2000..10000 steps, FP32)
+    under an HBM budget; reports p50/p99 time-to-result and throughput."""
+    from paper_2110_12448_amd import serve
+    reqs = serve.poisson_trace(n=args.requests)
+    budget = int(args.hbm_budget_gib * (1 << 30))
+    srv = serve.Server(hbm_budget_bytes=budget, chunk_steps=200, graph_steps=10)
+    t0 = time.perf_counter()
+    res = srv.run(reqs, realtime=True)
+    makespan = time.perf_counter() - t0
+    summ = serve.summarize(res, makespan, srv.busy_s)
+    out = {"metric": "served phi+U cell-updates/s; p50/p99 time-to-result", "value":
+           summ["cell_updates_per_s"], "unit": "cell-updates/s", "n_gpus": 1,
+           "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "served mix: Poisson arrivals mean 20/s, 80%% 2D 256^2-1024^2, "
+                                  "20%% 3D 128^3-192^3, 2000-10000 steps, FP32, HBM budget %.1f GiB"
+                                  % args.hbm_budget_gib, "requests": len(reqs)},
+           "serving": summ}
+    print(json.dumps(out))
+
+
 def load_counters(wk):
     """The committed rocprofv3 counter summary of the workload's step kernel,
     if it was taken on the current kernel source; else None."""
@@ -175,19 +198,21 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--launch-sample", type=int, default=None)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batched2d"],
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batched2d", "serve"],
                     default="directional2d")
+    ap.add_argument("--requests", type=int, default=100)
+    ap.add_argument("--hbm-budget-gib", type=float, default=2.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
         return
-    if args.workload == "batched2d":
+    if args.workload in ("batched2d", "serve"):
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
-        bench_batched(args)
+        (bench_batched if args.workload == "batched2d" else bench_serve)(args)
         return
     wk = WORKLOADS[args.workload]
     if args.steps is None:

@@ -1,0 +1,210 @@
+"""Continuous-batching request loop over the C ABI.
+
+Requests (one phase-field solve each: a problem dictionary, a step count and a
+precision) arrive over time.  The server keeps every admitted solve's fields
+resident in HBM, admits queued requests in arrival order whenever its HBM
+budget allows, and advances all active solves tick by tick: the active 2D
+solves of one kind share one batched launch per step (pf_batch_*), 3D solves
+are launched one after the other on the same stream.  A tick stops at the
+first step count an active solve needs, so every request receives exactly its
+steps; finished requests are read back and their memory released before the
+next admission.  Because batched stepping is bitwise identical to solo
+stepping, each result is the same alone and in the mix.
+
+All arithmetic runs in libpfiso.so; this module only schedules.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import time
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import pfiso
+from . import workloads as wl
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds on the trace clock
+    problem: dict
+    steps: int
+    precision: int = pfiso.PF_F32
+
+
+@dataclass
+class Result:
+    rid: int
+    arrival: float
+    admitted: float
+    finished: float
+    steps: int
+    cells: int
+    dim: int
+    fields: Optional[tuple] = None   # (phi, U, psi) if kept
+    tip: Optional[dict] = None
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+def workspace_bytes(prob: dict, precision: int) -> int:
+    lib = pfiso.load()
+    p, keep = pfiso.make_params(prob, precision)
+    return int(lib.pf_workspace_bytes(C.byref(p)))
+
+
+def _kind(prob: dict, precision: int):
+    return (precision, prob["lT"] > 0.0, int(prob["frame"]), np.asarray(prob["rot"]).reshape(-1, 9).shape[0] > 1)
+
+
+@dataclass
+class _Active:
+    req: Request
+    solver: pfiso.Solver
+    admitted: float
+    done: int = 0
+    nbytes: int = 0
+
+
+class Server:
+    def __init__(self, hbm_budget_bytes: int, chunk_steps: int = 200, device: str = "cuda:0",
+                 keep_fields: bool = False, graph_steps: int = 0):
+        self.budget = int(hbm_budget_bytes)
+        self.chunk = int(chunk_steps)
+        self.device = device
+        self.keep_fields = keep_fields
+        self.graph_steps = int(graph_steps)
+        self.busy_s = 0.0
+
+    def run(self, requests: List[Request], realtime: bool = True) -> List[Result]:
+        """Serve a finite trace.  realtime=False advances the trace clock to
+        the next arrival whenever the server is idle instead of sleeping, and
+        measures service on the wall clock otherwise (arrival times shift)."""
+        import torch
+        pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        queue: List[Request] = []
+        active: List[_Active] = []
+        results: List[Result] = []
+        used = 0
+        t0 = time.perf_counter()
+        skew = 0.0                       # idle time skipped in simulated mode
+        batches: Dict[tuple, tuple] = {}  # kind -> (member rids, pfiso.Batch)
+
+        def now():
+            return time.perf_counter() - t0 + skew
+
+        while pending or queue or active:
+            t = now()
+            while pending and pending[0].arrival <= t:
+                queue.append(pending.pop(0))
+            # admission by HBM budget, arrival order (a request larger than
+            # the whole budget is admitted alone)
+            while queue:
+                r = queue[0]
+                need = workspace_bytes(r.problem, r.precision)
+                if used + need > self.budget and active:
+                    break
+                queue.pop(0)
+                s = pfiso.Solver(r.problem, precision=r.precision, device=self.device)
+                active.append(_Active(r, s, now(), 0, need))
+                used += need
+            if not active:
+                if pending:
+                    wait = pending[0].arrival - now()
+                    if wait > 0:
+                        if realtime:
+                            time.sleep(wait)
+                        else:
+                            skew += wait
+                continue
+            # one tick: advance every active solve by the same number of steps
+            tick = min(self.chunk, min(a.req.steps - a.done for a in active))
+            tb = time.perf_counter()
+            groups: Dict[tuple, List[_Active]] = {}
+            for a in active:
+                if a.req.problem["dim"] == 2:
+                    groups.setdefault(_kind(a.req.problem, a.req.precision), []).append(a)
+            for kind, members in groups.items():
+                rids = tuple(m.req.rid for m in members)
+                if kind not in batches or batches[kind][0] != rids:
+                    if kind in batches:
+                        batches[kind][1].close()
+                    batches[kind] = (rids, pfiso.Batch([m.solver for m in members],
+                                                       graph_steps=self.graph_steps))
+                batches[kind][1].step(tick)
+            for kind in [k for k in batches if k not in groups]:
+                batches.pop(kind)[1].close()
+            for a in active:
+                if a.req.problem["dim"] == 3:
+                    a.solver.step(tick)
+                a.done += tick
+            torch.cuda.synchronize()
+            self.busy_s += time.perf_counter() - tb
+            # retire finished requests
+            still = []
+            for a in active:
+                if a.done < a.req.steps:
+                    still.append(a)
+                    continue
+                fields = None
+                if self.keep_fields:
+                    phi, U, psi, _ = a.solver.read_fields()
+                    fields = (phi, U, psi)
+                tip = a.solver.tip_state(allow_nonfinite=True)
+                res = Result(a.req.rid, a.req.arrival, a.admitted, now(), a.req.steps,
+                             int(np.prod(a.solver.shape)), a.req.problem["dim"], fields, tip)
+                results.append(res)
+                for kind in list(batches):
+                    if a.req.rid in batches[kind][0]:
+                        batches.pop(kind)[1].close()
+                a.solver.close()
+                used -= a.nbytes
+            active = still
+        for _, b in batches.values():
+            b.close()
+        return results
+
+
+def poisson_trace(n: int = 300, rate: float = 20.0, seed: int = 5, frac_3d: float = 0.2,
+                  steps=(2000, 10000), sides_2d=(256, 1024), sides_3d=(128, 160, 192),
+                  precision: int = pfiso.PF_F32) -> List[Request]:
+    """Seeded request trace: exponential inter-arrival times (mean 1/rate),
+    2D sides uniform on multiples of 64 in sides_2d, 3D sides from sides_3d,
+    step counts uniform in `steps`, misorientations uniform in [0, 45] deg."""
+    u = wl.uniform(seed, 11, 6 * n).reshape(n, 6)
+    t = 0.0
+    out = []
+    lo, hi = sides_2d[0] // 64, sides_2d[1] // 64
+    for i in range(n):
+        t += -np.log(1.0 - u[i, 0]) / rate
+        nst = int(steps[0] + u[i, 1] * (steps[1] - steps[0] + 1))
+        a0 = 45.0 * float(u[i, 2])
+        if u[i, 3] < frac_3d:
+            side = int(sides_3d[min(int(u[i, 4] * len(sides_3d)), len(sides_3d) - 1)])
+            rot = wl.random_rotations((seed * 7919 + i) & 0xFFFF, 1)
+            prob = wl.problem(3, (side, side, side), rot=rot, seed=(seed * 101 + i) & 0xFFFF,
+                              seed_shape="slab", seed_radius=5.0)
+        else:
+            side = 64 * (lo + min(int(u[i, 4] * (hi - lo + 1)), hi - lo))
+            prob = wl.problem(2, (side, side), alpha0_deg=a0, seed=(seed * 101 + i) & 0xFFFF)
+        out.append(Request(i, t, prob, nst, precision))
+    return out
+
+
+def summarize(results: List[Result], makespan: float, busy: float) -> dict:
+    """p50/p99 time-to-result, throughput, and the offered load: device-busy
+    time over the span of arrivals (> 1 means requests arrive faster than the
+    GPU can finish them, so queueing dominates the tail)."""
+    lat = np.array([r.latency for r in results])
+    work = float(sum(r.cells * r.steps for r in results))
+    span = max(r.arrival for r in results) - min(r.arrival for r in results)
+    return {"requests": len(results), "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)), "mean_latency_s": float(lat.mean()),
+            "makespan_s": makespan, "cell_updates_per_s": work / makespan,
+            "busy_fraction": busy / makespan, "arrival_span_s": span,
+            "offered_load": busy / span if span > 0 else None}
