@@ -52,7 +52,7 @@ class _Params(C.Structure):
         ("Vp", C.c_double), ("lT", C.c_double), ("y0", C.c_double),
         ("bc", C.c_int32 * 3), ("frame", C.c_int32), ("shift_row", C.c_int32),
         ("n_grains", C.c_int32), ("rot", C.POINTER(C.c_double)),
-        ("round_f32", C.c_int32),
+        ("round_f32", C.c_int32), ("antitrapping", C.c_int32), ("two_point", C.c_int32),
     ]
 
 
@@ -86,6 +86,9 @@ def _load():
         lib.or_step.argtypes = [pp, dp, dp, i8, C.c_int64, C.POINTER(_State)]
         lib.or_step.restype = C.c_int
         lib.or_tip_find.argtypes = [pp, dp, C.POINTER(_Tip)]
+        lib.or_divergence_two_point.argtypes = [pp, dp, dp, dp]
+        lib.or_antitrapping_full.argtypes = [pp, dp, dp, dp]
+        lib.or_flux_gradient_appB.argtypes = [pp, dp, C.c_long, C.c_long, C.c_int, dp, dp]
         lib.or_solid_fraction.argtypes = [pp, dp]
         lib.or_solid_fraction.restype = C.c_double
         lib.or_num_threads.restype = C.c_int
@@ -115,6 +118,8 @@ class Params:
     shift_row: int = 0
     rot: Optional[np.ndarray] = None   # (n_grains, 3, 3) crystal -> lab
     round_f32: int = 0
+    antitrapping: int = 0
+    two_point: int = 0
     _keep: list = field(default_factory=list, repr=False)
 
     @classmethod
@@ -143,6 +148,8 @@ class Params:
         cp.n_grains = rot.shape[0]
         cp.rot = rot.ctypes.data_as(C.POINTER(C.c_double))
         cp.round_f32 = int(self.round_f32)
+        cp.antitrapping = int(self.antitrapping)
+        cp.two_point = int(self.two_point)
         return cp
 
 
@@ -194,6 +201,34 @@ def divergence(p: Params, alpha, beta):
     cp = p._c()
     lib.or_divergence(C.byref(cp), _d(a), _d(b), _d(out))
     return out
+
+
+def divergence_two_point(p: Params, alpha, beta):
+    lib = _load()
+    a, b = _f64(p, alpha), _f64(p, beta)
+    out = np.empty_like(a)
+    cp = p._c()
+    lib.or_divergence_two_point(C.byref(cp), _d(a), _d(b), _d(out))
+    return out
+
+
+def antitrapping_full(p: Params, alpha, beta):
+    lib = _load()
+    a, b = _f64(p, alpha), _f64(p, beta)
+    out = np.empty_like(a)
+    cp = p._c()
+    lib.or_antitrapping_full(C.byref(cp), _d(a), _d(b), _d(out))
+    return out
+
+
+def flux_gradient_appB(p: Params, beta, i: int, j: int, direction: int):
+    lib = _load()
+    b = _f64(p, beta)
+    gx, gy = C.c_double(), C.c_double()
+    cp = p._c()
+    lib.or_flux_gradient_appB(C.byref(cp), _d(b), int(i), int(j), int(direction),
+                              C.byref(gx), C.byref(gy))
+    return gx.value, gy.value
 
 
 def anis_center(p: Params, psi, grain=None):

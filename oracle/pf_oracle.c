@@ -277,6 +277,146 @@ void or_divergence(const or_params *p, const double *alpha, const double *beta,
   }
 }
 
+/* Two-point divergence of the standard scheme S_{1,0} (Sec. 4.3.1, the
+ * <10> discretisation the paper takes from its Ref. Tourret 2015; READING:
+ * face alpha = mean of the two cells). */
+void or_divergence_two_point(const or_params *p, const double *alpha, const double *beta,
+                             double *out) {
+  const double h2 = p->h * p->h;
+  FOR_CELLS {
+    double a0 = F(alpha, 0, 0, 0), b0 = F(beta, 0, 0, 0);
+    double s = 0.0;
+    for (int ax = 0; ax < p->dim; ++ax)
+      for (int sg = -1; sg <= 1; sg += 2) {
+        int e[3] = {0, 0, 0};
+        e[ax] = sg;
+        s += (a0 + F(alpha, e[0], e[1], e[2])) / 2.0 * (F(beta, e[0], e[1], e[2]) - b0);
+      }
+    out[HERE] = s / h2;
+  }
+}
+
+/* ---------------------------------------------- full anti-trapping (App. B) */
+
+/* Rotate offset (a, b) by dir quarter turns counter-clockwise. */
+static void quarter(int q, int a, int b, int *x, int *y) {
+  for (int k = 0; k < q; ++k) {
+    int t = a;
+    a = -b;
+    b = t;
+  }
+  *x = a;
+  *y = b;
+}
+
+/* beta at cell (i, j) + (a, b) rotated by q quarter turns. */
+static double beta_rot(const or_params *p, const double *beta, long i, long j, int q, int a,
+                       int b) {
+  int x, y;
+  quarter(q, a, b, &x, &y);
+  const long l = 0;
+  return F(beta, x, y, 0);
+}
+
+/* App. B: |grad beta| at the flux points with vanishing O(h^2) error.  The
+ * formulas are printed for (1/2, 0) and (1/2, 1/2); the other points follow
+ * by rotating the stencil (the gradient rotates with it). */
+void or_flux_gradient_appB(const or_params *p, const double *beta, long i, long j, int dir,
+                           double *gx, double *gy) {
+  const double h = p->h;
+  int q = dir & 3;
+  double dx, dy;  /* derivatives in the rotated frame */
+#define BR(a, b) beta_rot(p, beta, i, j, q, (a), (b))
+  if (dir < 4) {
+    /* point (1/2, 0) of the rotated frame */
+    double t1 = (BR(1, 1) - BR(0, -1)) - (BR(0, 1) - BR(1, -1));
+    double t2 = (BR(2, 1) - BR(-1, -1)) - (BR(-1, 1) - BR(2, -1));
+    double t3 = (BR(1, 2) - BR(0, -2)) - (BR(0, 2) - BR(1, -2));
+    dx = 35.0 / 24.0 * t1 / (2.0 * h) - 1.0 / 8.0 * t2 / (6.0 * h) - 1.0 / 3.0 * t3 / (2.0 * h);
+    double u1 = (BR(1, 1) - BR(0, -1)) + (BR(0, 1) - BR(1, -1));
+    double u2 = (BR(2, 1) - BR(-1, -1)) + (BR(-1, 1) - BR(2, -1));
+    double u3 = (BR(1, 2) - BR(0, -2)) + (BR(0, 2) - BR(1, -2));
+    dy = 35.0 / 24.0 * u1 / (4.0 * h) - 1.0 / 8.0 * u2 / (4.0 * h) - 1.0 / 3.0 * u3 / (8.0 * h);
+  } else {
+    /* point (1/2, 1/2) of the rotated frame */
+    double t1 = (BR(1, 1) - BR(0, 0)) - (BR(0, 1) - BR(1, 0));
+    double t2 = (BR(2, 1) - BR(-1, 0)) - (BR(-1, 1) - BR(2, 0));
+    double t3 = (BR(1, 2) - BR(0, -1)) - (BR(0, 2) - BR(1, -1));
+    dx = 5.0 / 4.0 * t1 / (2.0 * h) - 1.0 / 8.0 * t2 / (6.0 * h) - 1.0 / 8.0 * t3 / (2.0 * h);
+    double u1 = (BR(1, 1) - BR(0, 0)) + (BR(0, 1) - BR(1, 0));
+    double u2 = (BR(2, 1) - BR(-1, 0)) + (BR(-1, 1) - BR(2, 0));
+    double u3 = (BR(1, 2) - BR(0, -1)) + (BR(0, 2) - BR(1, -1));
+    dy = 5.0 / 4.0 * u1 / (2.0 * h) - 1.0 / 8.0 * u2 / (2.0 * h) - 1.0 / 8.0 * u3 / (6.0 * h);
+  }
+#undef BR
+  /* back to the lattice frame: rotate (dx, dy) by q quarter turns */
+  double x = dx, y = dy;
+  for (int k = 0; k < q; ++k) {
+    double t = x;
+    x = -y;
+    y = t;
+  }
+  *gx = x;
+  *gy = y;
+}
+
+/* READING: a flux point whose |grad beta|^2 is at or below the guard carries
+ * no anti-trapping flux (the normal is undefined there). */
+static double inv_norm(double gx, double gy) {
+  double g2 = gx * gx + gy * gy;
+  return g2 > GRAD_EPS ? 1.0 / sqrt(g2) : 0.0;
+}
+
+/* Full anti-trapping term A = div(alpha grad beta / |grad beta|), 2D. */
+void or_antitrapping_full(const or_params *p, const double *alpha, const double *beta,
+                          double *out) {
+  const double h = p->h;
+  FOR_CELLS {
+#define A(a, b) F(alpha, a, b, 0)
+#define B(a, b) F(beta, a, b, 0)
+    double b0 = B(0, 0);
+    if (p->two_point) {
+      /* <10> fluxes: two-point alpha, face gradient from the normal difference
+       * and the tangential four-point average */
+      double s = 0.0;
+      for (int q = 0; q < 4; ++q) {
+        int ex, ey, tx, ty;
+        quarter(q, 1, 0, &ex, &ey);
+        quarter(q, 0, 1, &tx, &ty);
+        double gn = (B(ex, ey) - b0) / h;
+        double gt = (B(tx, ty) + B(ex + tx, ey + ty) - B(-tx, -ty) - B(ex - tx, ey - ty)) /
+                    (4.0 * h);
+        s += (A(0, 0) + A(ex, ey)) / 2.0 * gn * inv_norm(gn, gt) / h;
+      }
+      out[HERE] = s;
+    } else {
+      double s10 = 0.0, s01 = 0.0;
+      for (int q = 0; q < 4; ++q) {
+        /* <10> flux of Eq. flux_10): face alpha from the two cells and the two
+         * plaquettes beside the face */
+        int ex, ey, tx, ty;
+        quarter(q, 1, 0, &ex, &ey);
+        quarter(q, 0, 1, &tx, &ty);
+        double qp = (A(0, 0) + A(ex, ey) + A(tx, ty) + A(ex + tx, ey + ty)) / 4.0;
+        double qm = (A(0, 0) + A(ex, ey) + A(-tx, -ty) + A(ex - tx, ey - ty)) / 4.0;
+        double abar = (A(0, 0) + A(ex, ey) + qp + qm) / 4.0;
+        double gx, gy;
+        or_flux_gradient_appB(p, beta, i, j, q, &gx, &gy);
+        s10 += abar * (B(ex, ey) - b0) / h * inv_norm(gx, gy) / h;
+        /* <11> flux of Eq. flux_11): plaquette mean */
+        int dx, dy;
+        quarter(q, 1, 1, &dx, &dy);
+        double qd = (A(0, 0) + A(dx, 0) + A(0, dy) + A(dx, dy)) / 4.0;
+        or_flux_gradient_appB(p, beta, i, j, 4 + q, &gx, &gy);
+        s01 += qd * (B(dx, dy) - b0) / (SQRT2 * h) * inv_norm(gx, gy) / (SQRT2 * h);
+      }
+      out[HERE] = p->w[0] * s10 + p->w[1] * s01;
+    }
+#undef A
+#undef B
+  }
+}
+
 /* ------------------------------------------------------------ anisotropy */
 
 /* Cubic anisotropy of Eq. anis_function, rotated per grain.  READING (3D
@@ -389,7 +529,9 @@ void or_anis_remainder(const or_params *p, const double *psi,
  * isothermal limit F1 = 1, F2 = U (Sec. 2.1).
  * Approximated anti-trapping (Sec. 2.3): Abar = div(alpha_A grad psi) with
  * alpha_A = (1 + (1-k)U) d(phi)/dt / sqrt2 = (1 + (1-k)U)(1 - phi^2) dpsi/dt / 2.
- * The source term of Eq. PF_b equals sqrt2 alpha_A. */
+ * The source term of Eq. PF_b equals sqrt2 alpha_A.  With p->antitrapping the
+ * full current div(alpha_A grad psi/|grad psi|) of Eq. Anti_convention (App. B
+ * for its discretisation) replaces the approximated one. */
 void or_rates(const or_params *p, const double *psi, const double *U,
               const int8_t *grain, int64_t n, int64_t s, double *rate_psi,
               double *rate_U) {
@@ -430,8 +572,16 @@ void or_rates(const or_params *p, const double *psi, const double *U,
     aA[c] = (1.0 + (1.0 - k) * U[c]) * (1.0 - ph * ph) * rate_psi[c] / 2.0;
   }
 
-  or_divergence(p, aD, U, divD);
-  or_divergence(p, aA, psi, divA);
+  if (p->two_point)
+    or_divergence_two_point(p, aD, U, divD);
+  else
+    or_divergence(p, aD, U, divD);
+  if (p->antitrapping)
+    or_antitrapping_full(p, aA, psi, divA);
+  else if (p->two_point)
+    or_divergence_two_point(p, aA, psi, divA);
+  else
+    or_divergence(p, aA, psi, divA);
   for (size_t c = 0; c < nc; ++c) {
     double rhs = p->D * divD[c] + divA[c] + SQRT2 * aA[c];
     rate_U[c] = rhs / (1.0 + k - (1.0 - k) * phi[c]);

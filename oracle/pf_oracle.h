@@ -44,6 +44,10 @@ typedef struct or_params {
   int32_t n_grains;
   const double *rot;        /* n_grains x 9 row-major, crystal -> lab */
   int32_t round_f32;        /* 1: round stored psi, U to float after a step */
+  int32_t antitrapping;     /* 0: approximated current (Sec. 2.3); 1: full
+                               current of Eq. Anti_convention (2D only) */
+  int32_t two_point;        /* 1: standard <10> divergences with two-point
+                               face averages of alpha (2D scheme S_{1,0}) */
 } or_params;
 
 typedef struct or_tip {
@@ -65,6 +69,21 @@ void or_laplacian(const or_params *p, const double *psi, double *out);
 void or_grad_square(const or_params *p, const double *psi, double *out);
 void or_divergence(const or_params *p, const double *alpha, const double *beta,
                    double *out);
+/* Divergence with two-point face averages on the <10> (<100>) shell:
+ * (1/h^2) sum_faces (alpha_0 + alpha_e)/2 (beta_e - beta_0). */
+void or_divergence_two_point(const or_params *p, const double *alpha, const double *beta,
+                             double *out);
+/* Full anti-trapping divergence div(alpha grad(beta)/|grad beta|) (2D):
+ * shell fluxes of the divergence with |grad beta| at each flux point from the
+ * O(h^4) formulas of App. B (two_point = 0), or <10> fluxes with two-point
+ * alpha and the standard face gradient (two_point = 1). */
+void or_antitrapping_full(const or_params *p, const double *alpha, const double *beta,
+                          double *out);
+/* App. B gradient of beta at the flux point of cell (i, j) in direction
+ * dir: 0..3 = (+1/2,0), (0,+1/2), (-1/2,0), (0,-1/2); 4..7 = (+1/2,+1/2),
+ * (-1/2,+1/2), (-1/2,-1/2), (+1/2,-1/2). */
+void or_flux_gradient_appB(const or_params *p, const double *beta, long i, long j, int dir,
+                           double *gx, double *gy);
 void or_anis_center(const or_params *p, const double *psi, const int8_t *grain,
                     double *a_c);
 void or_anis_remainder(const or_params *p, const double *psi,
