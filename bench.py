@@ -40,6 +40,12 @@ ALG_BYTES_2D_F32 = 16
 ALG_FLOPS_3D = 1000
 # read psi, U, the int8 grain; write psi, U
 ALG_BYTES_3D_F32 = 17
+# FP32 operations per cell-update of the 2D step under the three schemes of
+# Table 1 (same counting rules; the full current adds three App. B gradients,
+# the two-point faces replace the shell divergences)
+SCHEME_FLOPS_2D = {"S10": 221, "S21": 319, "Sbar21": 237}
+# Table 1: wall time of the whole isothermal run on a Tesla P100 (context)
+PAPER_TABLE1_S = {"S10": 1359.0, "S21": 4612.0, "Sbar21": 3883.0}
 
 
 def src_digest(paths):
@@ -116,6 +122,77 @@ def bench_batched(args):
                       "cells": cells},
            "one_at_a_time_f32": cells * solo_steps / t32,
            "one_at_a_time_f64": cells * (solo_steps // 2) / t64}
+    print(json.dumps(out))
+
+
+def bench_schemes(args):
+    """The three 2D schemes of Table 1 on the isothermal free-growth run
+    (781^2, 20345 steps, FP32): the whole run timed per scheme, with the
+    per-launch kernel time and the FP64 oracle of S_{2,1} on a bounded sample."""
+    import numpy as np
+    import torch
+    from paper_2110_12448_amd import pfiso
+    from paper_2110_12448_amd import workloads as wl
+    steps = args.steps or wl.ISOTHERMAL_2D_STEPS
+    warm = args.warmup if args.warmup is not None else 200
+    nl = args.launch_sample or 200
+    out_s = {}
+    for name in ("S10", "S21", "Sbar21"):
+        pr = wl.config_isothermal_2d(**wl.SCHEMES_2D[name])
+        cells = pr["nx"] * pr["ny"]
+        s = pfiso.Solver(pr, precision=pfiso.PF_F32)
+        st = s.stream
+        print("bench: schemes2d %s %dx%d FP32, warmup %d, steps %d" %
+              (name, pr["nx"], pr["ny"], warm, steps), file=sys.stderr, flush=True)
+        s.step(warm)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        s.step(steps)
+        e1.record(st)
+        torch.cuda.synchronize()
+        run_s = e0.elapsed_time(e1) / 1e3
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(nl)]
+        for a, b in evs:
+            a.record(st)
+            s.step(1)
+            b.record(st)
+        torch.cuda.synchronize()
+        kern_ms = sum(a.elapsed_time(b) for a, b in evs) / nl
+        tip = s.tip_state()
+        s.close()
+        tf = SCHEME_FLOPS_2D[name] * cells / (kern_ms / 1e3) / 1e12
+        out_s[name] = {"run_s": run_s, "cell_updates_per_s": cells * steps / run_s,
+                       "kernel_ms": round(kern_ms, 5), "flops_per_cell": SCHEME_FLOPS_2D[name],
+                       "achieved_TFLOPs": round(tf, 3),
+                       "alu_frac": round(tf / PEAK_FP32_TFLOPS, 4),
+                       "tip_y": tip["y_lab"], "solid_fraction": tip["solid_fraction"],
+                       "paper_p100_run_s": PAPER_TABLE1_S[name]}
+    for name in out_s:
+        out_s[name]["time_vs_S10"] = round(out_s[name]["run_s"] / out_s["S10"]["run_s"], 3)
+    pr = wl.config_isothermal_2d(**wl.SCHEMES_2D["S21"])
+    cells = pr["nx"] * pr["ny"]
+    main_s = out_s["S21"]
+    cpu = None
+    if not args.no_cpu:
+        cpu, _, _, _, _ = cpu_baseline(pr, target_s=12.0, max_steps=200,
+                                       label="781^2 isothermal S_{2,1}")
+    tf = main_s["achieved_TFLOPs"]
+    out = {"metric": "phi+U cell-updates/s", "value": main_s["cell_updates_per_s"],
+           "unit": "cell-updates/s", "n_gpus": 1, "steps": steps, "warmup": warm,
+           "ms_per_step": main_s["run_s"] / steps * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "2D isothermal free growth, 781x781, h/W 1.2, W/d0* 16, "
+                                  "Omega 0.43, eps4 0.014, k 0.1, alpha0 30 deg, S_{2,1} (full "
+                                  "anti-trapping, App. B), FP32; S_{1,0} and S-bar_{2,1} beside",
+                      "nx": pr["nx"], "ny": pr["ny"], "h": pr["h"], "dt": pr["dt"]},
+           "roofline": {"bound": "alu", "achieved": tf, "peak": PEAK_FP32_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(tf / PEAK_FP32_TFLOPS, 4),
+                        "traffic": None, "kernel": "step2d_kernel<float,isothermal,full-AT>",
+                        "kernel_ms": main_s["kernel_ms"]},
+           "cpu_baseline": cpu, "schemes": out_s}
     print(json.dumps(out))
 
 
@@ -198,7 +275,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--launch-sample", type=int, default=None)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batched2d", "serve"],
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batched2d", "serve", "schemes2d"],
                     default="directional2d")
     ap.add_argument("--requests", type=int, default=100)
     ap.add_argument("--hbm-budget-gib", type=float, default=2.0)
@@ -208,11 +285,12 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
-    if args.workload in ("batched2d", "serve"):
+    if args.workload in ("batched2d", "serve", "schemes2d"):
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
-        (bench_batched if args.workload == "batched2d" else bench_serve)(args)
+        {"batched2d": bench_batched, "serve": bench_serve,
+         "schemes2d": bench_schemes}[args.workload](args)
         return
     wk = WORKLOADS[args.workload]
     if args.steps is None:

@@ -62,6 +62,21 @@ extern "C" {
 #define PF_SCHEME_STD 1          /* 2D (1, 0);     3D (1, 0, 0) */
 #define PF_SCHEME_WEIGHTS 2      /* pf_params.weights, normalised to sum 1 */
 
+/* anti-trapping current in Eq. PF_b (2D may take either; 3D is approximated
+ * only, as in Sec. 6: the full form would need a 3D analogue of App. B) */
+#define PF_AT_APPROX 0           /* div[alpha grad psi], Eq. Anti_approx (Sec. 2.3) */
+#define PF_AT_FULL 1             /* div[alpha grad psi / |grad psi|], Eq. Anti_convention;
+                                    with shell fluxes |grad psi| at each flux point
+                                    comes from the fourth-order stencils of App. B */
+
+/* discretisation of the two divergences of Eq. PF_b (2D only) */
+#define PF_DIV_SHELLS 0          /* shell fluxes with the scheme's weights (Sec. 4.1) */
+#define PF_DIV_TWO_POINT 1       /* <10> faces only, face alpha the mean of the two
+                                    cells and, for the full current, the face
+                                    gradient from the normal difference and the
+                                    four-point tangential difference: the standard
+                                    scheme S_{1,0} of Sec. 5 (with PF_SCHEME_STD) */
+
 typedef struct pf_params {
   int32_t dim;          /* 2 or 3 */
   int32_t nx, ny, nz;   /* lattice size, each >= 4 (nz ignored in 2D) */
@@ -82,6 +97,8 @@ typedef struct pf_params {
   int32_t shift_row;    /* frame moves one row when y_tip >= shift_row * h; 1..ny-2 */
   int32_t n_grains;     /* 1..127 */
   const double *grain_rot; /* n_grains x 9, row-major proper rotations, crystal -> lab */
+  int32_t antitrapping; /* PF_AT_APPROX (0, default) or PF_AT_FULL */
+  int32_t divergence;   /* PF_DIV_SHELLS (0, default) or PF_DIV_TWO_POINT */
 } pf_params;
 
 typedef struct pf_init {
@@ -172,7 +189,8 @@ void pf_destroy(pf_solver *s);
  * usable through the calls above (read-back, tip state, single steps); a
  * batch only needs its solvers to be alive, 2D, of one precision, of one kind
  * (all frozen or all isothermal, all with or without the moving frame, all
- * single- or all multi-grain) and bound to one stream.  Results are bitwise
+ * single- or all multi-grain), on the approximated current with shell
+ * divergences (the defaults) and bound to one stream.  Results are bitwise
  * those of stepping each solve on its own with the same launch geometry. */
 typedef struct pf_batch pf_batch;
 

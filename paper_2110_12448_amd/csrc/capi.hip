@@ -126,6 +126,12 @@ int validate(const pf_params *p) {
     if (p->dim == 2 && p->weights[2] != 0.0)
       return fail(PF_ERR_ARG, "2D has two shells: weights[2] must be 0");
   }
+  if (p->antitrapping != PF_AT_APPROX && p->antitrapping != PF_AT_FULL)
+    return fail(PF_ERR_ARG, "antitrapping must be PF_AT_APPROX or PF_AT_FULL");
+  if (p->divergence != PF_DIV_SHELLS && p->divergence != PF_DIV_TWO_POINT)
+    return fail(PF_ERR_ARG, "divergence must be PF_DIV_SHELLS or PF_DIV_TWO_POINT");
+  if (p->dim == 3 && (p->antitrapping != PF_AT_APPROX || p->divergence != PF_DIV_SHELLS))
+    return fail(PF_ERR_ARG, "3D runs the approximated current with shell divergences only");
   if (!(p->k > 0.0 && p->k < 1.0)) return fail(PF_ERR_ARG, "k must lie in (0, 1)");
   if (!(p->eps4 >= 0.0 && p->eps4 < 1.0 / 15.0))
     return fail(PF_ERR_ARG, "eps4 must lie in [0, 1/15)");
@@ -199,7 +205,7 @@ template <typename T>
 Coef<T> coef_of(const pf_solver *s) {
   const pf_params &p = s->p;
   const double h = p.h, h2 = h * h;
-  Coef<T> c;
+  Coef<T> c = {};
   c.dt = (T)s->dt;
   c.k = (T)p.k;
   c.omk = (T)(1.0 - p.k);
@@ -227,6 +233,14 @@ Coef<T> coef_of(const pf_solver *s) {
     c.cD1 = (T)(s->w[0] / (4.0 * h2));
     c.cD2 = (T)(s->w[1] / (2.0 * h2));
     c.cD3 = (T)0;
+    // full current: the same fluxes times h / |h grad psi| at the flux point
+    c.cA1 = (T)(s->w[0] / (4.0 * h));
+    c.cA2 = (T)(s->w[1] / (2.0 * h));
+    // two-point faces carry (alpha_0 + alpha_e) dbeta: /(2h^2); the full
+    // current times h / |h grad psi|: /(2h)
+    c.cT = (T)(1.0 / (2.0 * h2));
+    c.cTA = (T)(1.0 / (2.0 * h));
+    c.at_eps = (T)(1e-12 * h2);
   } else {
     // L_{1,0,0} = s/h^2, L_{0,1,0} = s/(4h^2), L_{0,0,1} = s/(4h^2)
     c.cL1 = (T)(s->w[0] / h2);
@@ -299,6 +313,9 @@ int step_impl(pf_solver *s, long long nsteps) {
     Step2DArgs<T> a;
     Geom2D g = fill2d<T>(s, a);
     (void)c;
+    const bool two = p.divergence == PF_DIV_TWO_POINT;
+    const int at = p.antitrapping == PF_AT_FULL ? (two ? kAtFullTwoPoint : kAtFullShells)
+                                                : (two ? kAtApproxTwoPoint : kAtApproxShells);
     for (long long i = 0; i < nsteps; ++i) {
       a.psi_in = field<T>(s, s->L.psi[s->cur]);
       a.U_in = field<T>(s, s->L.U[s->cur]);
@@ -308,7 +325,7 @@ int step_impl(pf_solver *s, long long nsteps) {
       a.frame_out = frec(s->fcur + 1);
       a.frame_clear = frec(s->fcur + 2);
       a.step = s->step;
-      PF_HIP(launch_step2d<T>(a, g, frozen, reduce, multi, s->stream));
+      PF_HIP(launch_step2d<T>(a, g, frozen, reduce, multi, at, s->stream));
       s->cur = 1 - s->cur;
       if (reduce) s->fcur = (s->fcur + 1) % 3;
       s->step += 1;
@@ -521,6 +538,8 @@ int pf_batch_create(pf_solver *const *solvers, int32_t n, pf_batch **out) {
   for (int i = 0; i < n; ++i) {
     const pf_solver *s = solvers[i];
     if (s->p.dim != 2) return fail(PF_ERR_ARG, "batched stepping is 2D only");
+    if (s->p.antitrapping != PF_AT_APPROX || s->p.divergence != PF_DIV_SHELLS)
+      return fail(PF_ERR_ARG, "batched stepping runs the approximated current on shell divergences");
     if (s->p.precision != s0->p.precision) return fail(PF_ERR_ARG, "mixed precisions in a batch");
     if ((s->p.lT > 0.0) != (s0->p.lT > 0.0) || (s->p.frame != 0) != (s0->p.frame != 0) ||
         (s->p.n_grains > 1) != (s0->p.n_grains > 1))

@@ -16,6 +16,7 @@ template <typename T> struct Math;
 
 template <> struct Math<float> {
   static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+  static __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
   // tanh(x) = sign(x) (1 - e) / (1 + e), e = exp(-2|x|), with the hardware
   // base-2 exponential; absolute error a few ulp of 1.
   static __device__ __forceinline__ float tanh_(float x) {
@@ -29,6 +30,7 @@ template <> struct Math<float> {
 
 template <> struct Math<double> {
   static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+  static __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
   static __device__ __forceinline__ double tanh_(double x) { return tanh(x); }
   static __device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
 };

@@ -54,6 +54,9 @@ struct Coef {
   T cStd;           // 1/h^2 (standard Laplacian of the eps4 remainder)
   T inv_lT;         // 1/lT (frozen temperature)
   T h;
+  T cA1, cA2;       // full anti-trapping on shell fluxes: cD1 h, cD2 h (2D)
+  T cT, cTA;        // two-point <10> faces: 1/(2h^2), and 1/(2h) for the full current
+  T at_eps;         // |grad psi|^2 h^2 at or below which a flux point carries no current
 };
 
 template <typename T>
@@ -128,9 +131,17 @@ size_t step3d_lds_bytes(int ztile, size_t elem);
 size_t tip_acc_bytes();
 int reduce_blocks(int nx, int ny, int nz);
 
+// Divergence / anti-trapping variants of the 2D step.
+enum At2D : int {
+  kAtApproxShells = 0,    // approximated current, shell fluxes (S-bar_{s1,s2})
+  kAtFullShells = 1,      // full current, App. B |grad psi| at the flux points (S_{2,1})
+  kAtFullTwoPoint = 2,    // full current, two-point <10> faces (S_{1,0})
+  kAtApproxTwoPoint = 3,  // approximated current, two-point <10> faces
+};
+
 template <typename T>
 hipError_t launch_step2d(const Step2DArgs<T> &a, const Geom2D &g, bool frozen, bool reduce,
-                         bool multi, hipStream_t st);
+                         bool multi, int at, hipStream_t st);
 template <typename T>
 hipError_t launch_step3d(const Step3DArgs<T> &a, const Geom3D &g, bool frozen, bool reduce,
                          bool multi, hipStream_t st);

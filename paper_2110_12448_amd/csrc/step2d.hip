@@ -23,6 +23,21 @@
 // between neighbouring cells are computed once: x-direction ones are passed
 // across lanes, y-direction ones carried to the next row.  Optionally the same
 // pass reduces the tip, solid fraction and finiteness of state n (FP64).
+//
+// Variants (template kAT) for the scheme comparison of Sec. 5 (Table 1):
+//   kAtApproxShells    the approximated current on shell fluxes (S-bar_{2,1});
+//   kAtFullShells      the full current div[alpha grad psi/|grad psi|] of
+//                      Eq. Anti_convention: each shell flux of the A
+//                      divergence divided by |grad psi| at its flux point, from
+//                      the fourth-order stencils of App. B (S_{2,1}).  These
+//                      reach rows q-2..q+2 and columns x-2..x+2 of the U row q,
+//                      so the window keeps two more psi rows and the +-2
+//                      columns of two rows; the 2-lane halo already covers them;
+//   kAtFullTwoPoint    both divergences on the <10> faces alone with the mean
+//                      of the two cells as face alpha, the full current with
+//                      the face gradient from the normal difference and the
+//                      four-point tangential difference (S_{1,0});
+//   kAtApproxTwoPoint  the same faces with the approximated current.
 #include <type_traits>
 
 #include "pf_device.hpp"
@@ -84,8 +99,9 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 }
 
 // One logical workgroup `lb` (4 waves) of the step of one solve `a`.
-template <typename T, bool kFrozen, bool kReduce, bool kMulti>
+template <typename T, bool kFrozen, bool kReduce, bool kMulti, int kAT>
 __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb) {
+  constexpr bool kTwoPoint = kAT == kAtFullTwoPoint || kAT == kAtApproxTwoPoint;
   using M = Math<T>;
   const Coef<T> &c = a.c;
   const int lane = threadIdx.x & 63;
@@ -134,6 +150,10 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
     // carries of the divergence for the row pair below (q-1, q)
     T cND = 0, c1D = 0, c2D = 0, cPD = 0;
     T cNA = 0, c1A = 0, c2A = 0, cPA = 0;
+    // full current only: B1 = row r-3, B2 = row r-4, and the x+-2 columns of
+    // rows r-1 (C) and r-2 (S)
+    T pB1 = 0, pB1W = 0, pB1E = 0, pB1E2 = 0, pB2 = 0, pB2E = 0;
+    T pCE2 = 0, pCW2 = 0, pSE2 = 0, pSW2 = 0;
 
     // rows r, r+1, r+2 in flight (loads issued two iterations ahead)
     T lp0, lu0, lp1, lu1, lp2, lu2;
@@ -152,6 +172,13 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
     // the steady state with every stage active.
     auto iter = [&](auto phase, int r) {
       constexpr int P = decltype(phase)::value;
+      if constexpr (kAT == kAtFullShells) {
+        pB2 = pB1; pB2E = pB1E; pB1E2 = pSE2;
+        pSE2 = pCE2; pSW2 = pCW2;
+      }
+      if constexpr (kAT == kAtFullShells || kAT == kAtFullTwoPoint) {
+        pB1 = pS; pB1W = pSW; pB1E = pSE;
+      }
       pS = pC; pSW = pCW; pSE = pCE;
       pC = pN; pCW = pNW; pCE = pNE;
       uS = uC; uC = uN;
@@ -171,6 +198,10 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
       pNE = from_right(pN);
       fN = M::tanh_(pN * isq2);
       if constexpr (P == 0) return;
+      if constexpr (kAT == kAtFullShells && P >= 2) {
+        pCE2 = from_right(pCE);
+        pCW2 = from_left(pCW);
+      }
 
       // y face between rows r-1 and r, grain of the lower cell
       T FyN;
@@ -229,7 +260,34 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
       }
       FyS = FyN;
 
-      if constexpr (P >= 3) {
+      if constexpr (P >= 3 && kTwoPoint) {
+        // ---------------- <10> faces of row q = r-2: east face and north face
+        const int q = r - 2;
+        T aq = T(1) - fS, aq1 = T(1) - fC;
+        T fED = (aq + from_right(aq)) * (from_right(uS) - uS);
+        T fND = (aq + aq1) * (uC - uS);
+        T dE = pSE - pS, dN = pC - pS;
+        T fEA = (aAS + from_right(aAS)) * dE;
+        T fNA = (aAS + aAC) * dN;
+        if constexpr (kAT == kAtFullTwoPoint) {
+          // |grad psi| h at the faces: normal difference and a quarter of the
+          // four-point tangential difference
+          T tE = pC + pCE - pB1 - pB1E;
+          T tN = pSW + pCW - pSE - pCE;
+          T gE = dE * dE + T(0.0625) * (tE * tE);
+          T gN = dN * dN + T(0.0625) * (tN * tN);
+          fEA *= gE > c.at_eps ? M::rsq(gE) : T(0);
+          fNA *= gN > c.at_eps ? M::rsq(gN) : T(0);
+        }
+        if constexpr (P == 4) {
+          T divD = c.cT * (fED - from_left(fED) + fND - cND);
+          T divA = (kAT == kAtFullTwoPoint ? c.cTA : c.cT) * (fEA - from_left(fEA) + fNA - cNA);
+          T rU = (c.D * divD + divA + sq2 * aAS) * M::rcp(T(1) + c.k - c.omk * fS);
+          if (out_lane) a.U_out[(size_t)q * (size_t)nx + (size_t)x] = uS + c.dt * rU;
+        }
+        cND = fND;
+        cNA = fNA;
+      } else if constexpr (P >= 3) {
         // ---------------- divergences on the row pair (q, q+1) = (S, C), q = r-2
         // field D: alpha = 1 - phi, beta = U;  field A: alpha = alpha_A, beta = psi
         const int q = r - 2;
@@ -249,12 +307,55 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
         T fNA = (aAS + aAC + PA + PAW) * (pC - pS);
         T d1A = PA * (pCE - pS), d2A = PAW * (pCW - pS);
 
+        if constexpr (kAT == kAtFullShells) {
+          // App. B gradients (times h) at the north face (q+1/2), the north-east
+          // corner (q+1/2, x+1/2) and, for the U row, the east face (q, x+1/2);
+          // the west, north-west and south fluxes reuse the neighbours' values
+          auto inv = [&](T gx, T gy) {
+            T g2 = gx * gx + gy * gy;
+            return g2 > c.at_eps ? M::rsq(g2) : T(0);
+          };
+          const T k1 = T(35.0 / 48.0), k2 = T(1.0 / 48.0), k3 = T(1.0 / 6.0);
+          const T m1 = T(35.0 / 96.0), m2 = T(1.0 / 32.0), m3 = T(1.0 / 24.0);
+          T invN;
+          {  // face (0, 1/2): the (1/2, 0) stencil turned a quarter
+            T a1 = pCW - pSE, b1 = pCE - pSW;
+            T a2 = pNW - pB1E, b2 = pNE - pB1W;
+            T a3 = pCW2 - pSE2, b3 = pCE2 - pSW2;
+            T gx = k1 * (a1 + b1) - k2 * (a2 + b2) - k3 * (a3 + b3);
+            T gy = m1 * (a1 - b1) - m2 * (a2 - b2) - m3 * (a3 - b3);
+            invN = inv(gx, gy);
+          }
+          T invNE;
+          {  // corner (1/2, 1/2)
+            T a1 = pCE - pS, b1 = pSE - pC;
+            T a2 = pCE2 - pSW, b2 = pSE2 - pCW;
+            T a3 = pNE - pB1, b3 = pB1E - pN;
+            T gx = T(5.0 / 8.0) * (a1 + b1) - T(1.0 / 48.0) * (a2 + b2) - T(1.0 / 16.0) * (a3 + b3);
+            T gy = T(5.0 / 8.0) * (a1 - b1) - T(1.0 / 16.0) * (a2 - b2) - T(1.0 / 48.0) * (a3 - b3);
+            invNE = inv(gx, gy);
+          }
+          fNA *= invN;
+          d1A *= invNE;
+          d2A *= from_left(invNE);
+          if constexpr (P == 4) {  // face (1/2, 0)
+            T a1 = pCE - pB1, b1 = pB1E - pC;
+            T a2 = pCE2 - pB1W, b2 = pB1E2 - pCW;
+            T a3 = pNE - pB2, b3 = pB2E - pN;
+            T gx = k1 * (a1 + b1) - k2 * (a2 + b2) - k3 * (a3 + b3);
+            T gy = m1 * (a1 - b1) - m2 * (a2 - b2) - m3 * (a3 - b3);
+            fEA *= inv(gx, gy);
+          }
+        }
+
         if constexpr (P == 4) {
+          constexpr bool kF = kAT == kAtFullShells;
           T fWD = -from_left(fED), fWA = -from_left(fEA);
           T swD = -from_left(c1D), seD = -from_right(c2D);
           T swA = -from_left(c1A), seA = -from_right(c2A);
           T divD = c.cD1 * (fED + fWD + fND - cND) + c.cD2 * (d1D + d2D + swD + seD);
-          T divA = c.cD1 * (fEA + fWA + fNA - cNA) + c.cD2 * (d1A + d2A + swA + seA);
+          T divA = (kF ? c.cA1 : c.cD1) * (fEA + fWA + fNA - cNA) +
+                   (kF ? c.cA2 : c.cD2) * (d1A + d2A + swA + seA);
           T rU = (c.D * divD + divA + sq2 * aAS) * M::rcp(T(1) + c.k - c.omk * fS);
           if (out_lane) a.U_out[(size_t)q * (size_t)nx + (size_t)x] = uS + c.dt * rU;
         }
@@ -289,9 +390,9 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
   }
 }
 
-template <typename T, bool kFrozen, bool kReduce, bool kMulti>
+template <typename T, bool kFrozen, bool kReduce, bool kMulti, int kAT>
 __global__ __launch_bounds__(256) void step2d_kernel(Step2DArgs<T> a) {
-  step2d_body<T, kFrozen, kReduce, kMulti>(a, xcd_remap((int)blockIdx.x, (int)gridDim.x));
+  step2d_body<T, kFrozen, kReduce, kMulti, kAT>(a, xcd_remap((int)blockIdx.x, (int)gridDim.x));
 }
 
 // Many solves in one launch: workgroup b runs logical workgroup map[b].y of
@@ -316,7 +417,7 @@ __global__ __launch_bounds__(256) void batch2d_kernel(const BatchSolve2D<T> *tab
     a.frame_out = e.frames[(f + 1) % 3];
     a.frame_clear = e.frames[(f + 2) % 3];
   }
-  step2d_body<T, kFrozen, kReduce, kMulti>(a, bm.y);
+  step2d_body<T, kFrozen, kReduce, kMulti, kAtApproxShells>(a, bm.y);
 }
 
 // Advance the epoch origin of every solve by `steps` (end of a captured graph).
@@ -343,12 +444,12 @@ Geom2D geom2d(int nx, int ny, int seg) {
   return g;
 }
 
-template <typename T>
-hipError_t launch_step2d(const Step2DArgs<T> &a, const Geom2D &g, bool frozen, bool reduce,
-                         bool multi, hipStream_t st) {
+template <typename T, int kAT>
+void launch_step2d_at(const Step2DArgs<T> &a, const Geom2D &g, bool frozen, bool reduce,
+                      bool multi, hipStream_t st) {
   dim3 grid(g.blocks), block(256);
 #define PF_L2(F, R, MU) \
-  hipLaunchKernelGGL((step2d_kernel<T, F, R, MU>), grid, block, 0, st, a)
+  hipLaunchKernelGGL((step2d_kernel<T, F, R, MU, kAT>), grid, block, 0, st, a)
   if (frozen) {
     if (reduce) { if (multi) PF_L2(true, true, true); else PF_L2(true, true, false); }
     else { if (multi) PF_L2(true, false, true); else PF_L2(true, false, false); }
@@ -357,6 +458,20 @@ hipError_t launch_step2d(const Step2DArgs<T> &a, const Geom2D &g, bool frozen, b
     else { if (multi) PF_L2(false, false, true); else PF_L2(false, false, false); }
   }
 #undef PF_L2
+}
+
+template <typename T>
+hipError_t launch_step2d(const Step2DArgs<T> &a, const Geom2D &g, bool frozen, bool reduce,
+                         bool multi, int at, hipStream_t st) {
+  switch (at) {
+    case kAtApproxShells: launch_step2d_at<T, kAtApproxShells>(a, g, frozen, reduce, multi, st); break;
+    case kAtFullShells: launch_step2d_at<T, kAtFullShells>(a, g, frozen, reduce, multi, st); break;
+    case kAtFullTwoPoint: launch_step2d_at<T, kAtFullTwoPoint>(a, g, frozen, reduce, multi, st); break;
+    case kAtApproxTwoPoint:
+      launch_step2d_at<T, kAtApproxTwoPoint>(a, g, frozen, reduce, multi, st);
+      break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -395,8 +510,8 @@ template hipError_t launch_batch2d_advance<double>(BatchSolve2D<double> *, int, 
                                                    hipStream_t);
 
 template hipError_t launch_step2d<float>(const Step2DArgs<float> &, const Geom2D &, bool, bool,
-                                         bool, hipStream_t);
+                                         bool, int, hipStream_t);
 template hipError_t launch_step2d<double>(const Step2DArgs<double> &, const Geom2D &, bool, bool,
-                                          bool, hipStream_t);
+                                          bool, int, hipStream_t);
 
 }  // namespace pf

@@ -30,6 +30,8 @@ PF_ERR_STATE = -6
 PF_F32, PF_F64 = 0, 1
 PF_BC_NOFLUX, PF_BC_PERIODIC = 0, 1
 PF_SCHEME_ISO, PF_SCHEME_STD, PF_SCHEME_WEIGHTS = 0, 1, 2
+PF_AT_APPROX, PF_AT_FULL = 0, 1
+PF_DIV_SHELLS, PF_DIV_TWO_POINT = 0, 1
 
 EXPORTED = ("pf_version", "pf_last_error", "pf_stable_dt", "pf_workspace_bytes", "pf_create",
             "pf_step", "pf_synchronize", "pf_read_fields", "pf_tip_state", "pf_device_fields",
@@ -46,6 +48,7 @@ class pf_params(C.Structure):
         ("y0", C.c_double), ("bc", C.c_int32 * 3), ("frame", C.c_int32),
         ("shift_row", C.c_int32), ("n_grains", C.c_int32),
         ("grain_rot", C.POINTER(C.c_double)),
+        ("antitrapping", C.c_int32), ("divergence", C.c_int32),
     ]
 
 
@@ -141,6 +144,8 @@ def make_params(prob: dict, precision: int = PF_F32, scheme: Optional[int] = Non
     p.frame, p.shift_row = int(prob["frame"]), int(prob["shift_row"])
     p.n_grains = rot.shape[0]
     p.grain_rot = rot.ctypes.data_as(C.POINTER(C.c_double))
+    p.antitrapping = int(prob.get("antitrapping", PF_AT_APPROX))
+    p.divergence = PF_DIV_TWO_POINT if prob.get("two_point", 0) else PF_DIV_SHELLS
     return p, rot
 
 

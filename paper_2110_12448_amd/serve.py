@@ -4,8 +4,9 @@ Requests (one phase-field solve each: a problem dictionary, a step count and a
 precision) arrive over time.  The server keeps every admitted solve's fields
 resident in HBM, admits queued requests in arrival order whenever its HBM
 budget allows, and advances all active solves tick by tick: the active 2D
-solves of one kind share one batched launch per step (pf_batch_*), 3D solves
-are launched one after the other on the same stream.  A tick stops at the
+solves of one kind share one batched launch per step (pf_batch_*); 3D solves
+and 2D solves on the full anti-trapping current or two-point divergences are
+launched one after the other on the same stream.  A tick stops at the
 first step count an active solve needs, so every request receives exactly its
 steps; finished requests are read back and their memory released before the
 next admission.  Because batched stepping is bitwise identical to solo
@@ -56,6 +57,11 @@ def workspace_bytes(prob: dict, precision: int) -> int:
     lib = pfiso.load()
     p, keep = pfiso.make_params(prob, precision)
     return int(lib.pf_workspace_bytes(C.byref(p)))
+
+
+def _batchable(prob: dict) -> bool:
+    """Batched launches run the approximated current on shell divergences."""
+    return prob["dim"] == 2 and not prob.get("antitrapping", 0) and not prob.get("two_point", 0)
 
 
 def _kind(prob: dict, precision: int):
@@ -127,7 +133,7 @@ class Server:
             tb = time.perf_counter()
             groups: Dict[tuple, List[_Active]] = {}
             for a in active:
-                if a.req.problem["dim"] == 2:
+                if _batchable(a.req.problem):
                     groups.setdefault(_kind(a.req.problem, a.req.precision), []).append(a)
             for kind, members in groups.items():
                 rids = tuple(m.req.rid for m in members)
@@ -140,7 +146,7 @@ class Server:
             for kind in [k for k in batches if k not in groups]:
                 batches.pop(kind)[1].close()
             for a in active:
-                if a.req.problem["dim"] == 3:
+                if not _batchable(a.req.problem):
                     a.solver.step(tick)
                 a.done += tick
             torch.cuda.synchronize()

@@ -139,12 +139,15 @@ def problem(dim: int, shape: Sequence[int], *, h: float = 0.8, k: float = 0.15,
             omega: float = 0.55, bc: Optional[Sequence[int]] = None,
             frame: int = 0, shift_row: Optional[int] = None,
             seed_shape: str = "disc", seed_radius: float = 10.0,
-            noise: float = 0.01, seed: int = 1) -> dict:
+            noise: float = 0.01, seed: int = 1, antitrapping: int = 0,
+            two_point: int = 0) -> dict:
     """One solve: scalar parameters plus initial psi, U and grain arrays.
 
     shape is (nx, ny) in 2D and (nx, ny, nz) in 3D.  seed_shape 'disc' puts a
     disc (sphere) of radius seed_radius*h centred at ((nx/2) h, 0[, (nz/2) h]);
-    'slab' puts the solid at y <= seed_radius*h.  thermal 'frozen' uses the
+    'slab' puts the solid at y <= seed_radius*h.  antitrapping 1 selects the
+    full current of Eq. Anti_convention (2D), two_point 1 the two-point <10>
+    divergences of the standard scheme (2D).  thermal 'frozen' uses the
     frozen-temperature functions with U from a uniform c_inf = k c_l^0 (U = -1 in
     the liquid, 0 in the solid); 'isothermal' uses F1 = 1, F2 = U with U = -omega
     everywhere.
@@ -202,7 +205,16 @@ def problem(dim: int, shape: Sequence[int], *, h: float = 0.8, k: float = 0.15,
     return dict(dim=dim, nx=nx, ny=ny, nz=nz, w=tuple(w), k=k, eps4=eps4, D=D, lam=lam,
                 h=h, dt=dt, Vp=Vp, lT=lT, y0=y0, bc=tuple(bc), frame=int(frame),
                 shift_row=int(ny // 2 if shift_row is None else shift_row), rot=rot,
-                psi0=psi0, U0=U0, grain=grain)
+                psi0=psi0, U0=U0, grain=grain, antitrapping=int(antitrapping),
+                two_point=int(two_point))
+
+
+# The three 2D schemes compared in Sec. 5 (Table 1), as problem() keywords.
+SCHEMES_2D = {
+    "S10": dict(scheme="std", antitrapping=1, two_point=1),   # anisotropic, full A
+    "S21": dict(scheme="iso", antitrapping=1),                # isotropic, full A (App. B)
+    "Sbar21": dict(scheme="iso"),                             # isotropic, approximated A
+}
 
 
 # ------------------------------------------------------------------ configs
@@ -211,6 +223,27 @@ def config_small_2d(alpha0_deg: float = 0.0, n: int = 128, seed: int = 1, **kw) 
     """128 x 128, h = 0.8, k = 0.15, eps4 = 0.02, D = 2, frozen gradient, disc
     seed of radius 10 h at the bottom with +-0.01 phi noise."""
     return problem(2, (n, n), alpha0_deg=alpha0_deg, seed=seed, **kw)
+
+
+def config_isothermal_2d(alpha0_deg: float = 30.0, n: int = 781, seed: int = 6, **kw) -> dict:
+    """Free growth in an isothermal melt as in the runs behind Table 1
+    (Sec. 5): W/d0* = 16, h/W = 1.2, eps4 = 0.014, k = 0.1, Omega = 0.43,
+    no-flux walls on a square of side 1.5e4 d0* (781 cells), circular seed of
+    radius 50 d0* at the centre.  lambda = a1 W/d0*, D~ = a2 lambda
+    (Sec. 2.1), dt = 0.8 h^2 / (4 D~).  The whole run, t = 1.5e6 d0*^2/D, is
+    ISOTHERMAL_2D_STEPS steps."""
+    lam = A1 * 16.0
+    D = A2 * lam
+    h = 1.2
+    kw.setdefault("bc", (NOFLUX, NOFLUX, NOFLUX))
+    return problem(2, (n, n), h=h, k=0.1, eps4=0.014, D=D, lam=lam, dt=stable_dt(2, h, D),
+                   thermal="isothermal", omega=0.43, alpha0_deg=alpha0_deg,
+                   seed_radius=50.0 / 16.0 / h, y_front=(n // 2) * h, seed=seed, **kw)
+
+
+# t = 1.5e6 d0*^2 / D = 1.5e6 tau_0 / ((W/d0*)^2 D~) since D = D~ W^2 / tau_0
+ISOTHERMAL_2D_STEPS = int(round(1.5e6 / (16.0 ** 2 * (A2 * A1 * 16.0) *
+                                         stable_dt(2, 1.2, A2 * A1 * 16.0))))
 
 
 def misorientation(seed: int) -> float:

@@ -32,8 +32,8 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    # pf_params: 6 int32, 3 doubles, 9 doubles, 3+3 int32, pointer -> 8-aligned
-    assert C.sizeof(pfiso.pf_params) == 4 * 6 + 8 * 3 + 8 * 9 + 4 * 6 + 8
+    # pf_params: 6 int32, 3 doubles, 9 doubles, 3+3 int32, pointer, 2 int32
+    assert C.sizeof(pfiso.pf_params) == 4 * 6 + 8 * 3 + 8 * 9 + 4 * 6 + 8 + 4 * 2
     assert C.sizeof(pfiso.pf_tip) == 8 + 8 + 4 + 4 + 8 + 8 * 6 + 8
 
 
@@ -82,6 +82,7 @@ def test_stable_dt_and_workspace():
     (dict(lT=10.0, y0=-100.0), pfiso.PF_ERR_ARG, "F1"),
     (dict(rot=np.diag([1.0, 1.0, -1.0])[None]), pfiso.PF_ERR_ARG, "improper"),
     (dict(rot=wl.random_rotations(3, 1)), pfiso.PF_ERR_ARG, "about z"),
+    (dict(antitrapping=2), pfiso.PF_ERR_ARG, "antitrapping"),
 ])
 def test_create_rejects_bad_parameters(over, code, needle):
     rc, msg, _ = _create(_params(**over))
@@ -110,3 +111,22 @@ def test_frame_requires_columnar_grains():
     pr["grain"] = g
     rc, msg, _ = _create(pr)
     assert rc == pfiso.PF_ERR_ARG and "along y" in msg
+
+
+def test_scheme_fields_validated():
+    lib = pfiso.load()
+    pr = _params()
+    p, keep = pfiso.make_params(pr)
+    p.divergence = 3
+    assert lib.pf_stable_dt(C.byref(p)) < 0
+    assert "divergence" in lib.pf_last_error().decode()
+    pr3 = wl.problem(3, (8, 8, 8), antitrapping=1)
+    p3, keep3 = pfiso.make_params(pr3)
+    assert lib.pf_stable_dt(C.byref(p3)) < 0
+    assert "3D" in lib.pf_last_error().decode()
+    pr3 = wl.problem(3, (8, 8, 8), two_point=1)
+    p3, keep3 = pfiso.make_params(pr3)
+    assert lib.pf_stable_dt(C.byref(p3)) < 0
+    for name, kw in wl.SCHEMES_2D.items():
+        p2, keep2 = pfiso.make_params(wl.problem(2, (16, 16), **kw))
+        assert lib.pf_stable_dt(C.byref(p2)) > 0, (name, lib.pf_last_error().decode())
