@@ -61,16 +61,30 @@ WORKLOADS = {
         sources=["paper_2110_12448_amd/csrc/step2d.hip", "paper_2110_12448_amd/csrc/pf_device.hpp"],
         counters="profiles/step2d_directional_1024x2048_counters.json",
         kernel="step2d_kernel<float,frozen,frame>", flops=ALG_FLOPS_2D, bytes=ALG_BYTES_2D_F32,
-        steps=20000, warmup=500,
+        steps=20000, warmup=500, build=lambda wl: wl.config_directional_2d(),
         text="2D directional solidification, moving frame, 1024x2048, S-bar_{2,1}, FP32 "
              "fields, FP64 tip/fraction reductions"),
+    "directional2d_8192": dict(
+        sources=["paper_2110_12448_amd/csrc/step2d.hip", "paper_2110_12448_amd/csrc/pf_device.hpp"],
+        counters="profiles/step2d_directional_8192x8192_counters.json",
+        kernel="step2d_kernel<float,frozen,frame>", flops=ALG_FLOPS_2D, bytes=ALG_BYTES_2D_F32,
+        steps=1000, warmup=50, cpu_steps=2,
+        build=lambda wl: wl.config_directional_2d(nx=8192, ny=8192),
+        text="2D directional solidification, moving frame, 8192x8192 (1 GiB of fields, beyond "
+             "the 256 MB last-level cache), S-bar_{2,1}, FP32"),
     "polycrystal3d": dict(
         sources=["paper_2110_12448_amd/csrc/step3d.hip", "paper_2110_12448_amd/csrc/pf_device.hpp"],
         counters="profiles/step3d_polycrystal_256cubed_counters.json",
         kernel="step3d_kernel<float,frozen,multigrain>", flops=ALG_FLOPS_3D, bytes=ALG_BYTES_3D_F32,
-        steps=300, warmup=20,
+        steps=300, warmup=20, cpu_steps=3, build=lambda wl: wl.config_polycrystal_3d(),
         text="3D polycrystal, 256^3, 8 Voronoi grains with uniform random cubic orientations, "
              "S-bar_{1,2,0}, FP32 fields"),
+    "polycrystal3d_512": dict(
+        sources=["paper_2110_12448_amd/csrc/step3d.hip", "paper_2110_12448_amd/csrc/pf_device.hpp"],
+        counters="profiles/step3d_polycrystal_512cubed_counters.json",
+        kernel="step3d_kernel<float,frozen,multigrain>", flops=ALG_FLOPS_3D, bytes=ALG_BYTES_3D_F32,
+        steps=40, warmup=4, cpu_steps=1, build=lambda wl: wl.config_polycrystal_3d(n=512),
+        text="3D polycrystal, 512^3 (2.1 GiB of fields), 8 Voronoi grains, S-bar_{1,2,0}, FP32"),
 }
 
 
@@ -250,8 +264,21 @@ def copy_calibration(nbytes=1 << 30, reps=20):
                       "ms_per_copy": ms, "GBs_read_plus_write": 2 * nbytes / ms / 1e6}))
 
 
+def _host_cpu():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "model": model}
+
+
 def cpu_baseline(pr, target_s=12.0, max_steps=40, label="1024x2048 directional"):
-    import numpy as np
+    """The FP64 oracle on the host: steps of the same solve until target_s or
+    max_steps, on all OpenMP threads; then a shorter single-thread sample."""
     import oracle
     p = oracle.Params.from_problem(pr)
     psi, U, g = pr["psi0"], pr["U0"], pr["grain"]
@@ -263,10 +290,24 @@ def cpu_baseline(pr, target_s=12.0, max_steps=40, label="1024x2048 directional")
         steps += 1
     dt = time.perf_counter() - t0
     cells = pr["nx"] * pr["ny"] * pr["nz"]
-    return {"value": cells * steps / dt, "unit": "cell-updates/s", "cores": oracle.num_threads(),
+    threads = oracle.num_threads()
+    # single thread: at least one step, at most a quarter of the budget
+    oracle.set_num_threads(1)
+    t1 = time.perf_counter()
+    s1 = 0
+    q, V, st1 = pr["psi0"], pr["U0"], oracle.State()
+    while s1 < 1 or (s1 < max_steps and (time.perf_counter() - t1) < target_s / 4):
+        q, V, st1 = oracle.step(p, q, V, g, 1, st1)
+        s1 += 1
+    dt1 = time.perf_counter() - t1
+    oracle.set_num_threads(threads)
+    return {"value": cells * steps / dt, "unit": "cell-updates/s", "cores": threads,
             "kind": "oracle",
             "sample": "FP64 oracle, first %d steps of the same %s solve "
-                      "(%.1f s)" % (steps, label, dt)}, steps, psi, U, st
+                      "(%.1f s)" % (steps, label, dt),
+            "single_thread_value": cells * s1 / dt1,
+            "single_thread_sample": "%d steps (%.1f s)" % (s1, dt1),
+            "host": _host_cpu()}, steps, psi, U, st
 
 
 def main():
@@ -311,10 +352,7 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    if args.workload == "directional2d":
-        pr = wl.config_directional_2d()
-    else:
-        pr = wl.config_polycrystal_3d()
+    pr = wk["build"](wl)
     cells = pr["nx"] * pr["ny"] * pr["nz"]
     s = pfiso.Solver(pr, precision=pfiso.PF_F32, device="cuda:0")
     st = s.stream
@@ -365,11 +403,12 @@ def main():
     cpu = None
     err = None
     if not args.no_cpu:
-        if args.workload == "directional2d":
+        if "cpu_steps" not in wk:
             cpu, nst, opsi, oU, ost = cpu_baseline(pr)
         else:
-            cpu, nst, opsi, oU, ost = cpu_baseline(pr, target_s=15.0, max_steps=3,
-                                                   label="256^3 polycrystal")
+            cpu, nst, opsi, oU, ost = cpu_baseline(pr, target_s=15.0, max_steps=wk["cpu_steps"],
+                                                   label=wk["text"].split(",")[0] + " %dx%dx%d" % (
+                                                       pr["nx"], pr["ny"], pr["nz"]))
         # the same number of steps on the GPU, compared with the oracle state
         s2 = pfiso.Solver(pr, precision=pfiso.PF_F32, device="cuda:0")
         s2.step(nst)

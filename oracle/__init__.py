@@ -92,6 +92,7 @@ def _load():
         lib.or_solid_fraction.argtypes = [pp, dp]
         lib.or_solid_fraction.restype = C.c_double
         lib.or_num_threads.restype = C.c_int
+        lib.or_set_num_threads.argtypes = [C.c_int]
         _lib = lib
     return _lib
 
@@ -303,3 +304,7 @@ def solid_fraction(p: Params, phi_field) -> float:
 
 def num_threads() -> int:
     return int(_load().or_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    _load().or_set_num_threads(int(n))

@@ -39,6 +39,14 @@ int or_num_threads(void) {
 #endif
 }
 
+void or_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ---------------------------------------------------------------- ghosts */
 
 /* Boundary ghost map of one axis.  PERIODIC wraps; NOFLUX mirrors about the

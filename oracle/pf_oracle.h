@@ -103,6 +103,8 @@ void or_tip_find(const or_params *p, const double *phi, or_tip *out);
 double or_solid_fraction(const or_params *p, const double *phi);
 
 int or_num_threads(void);
+/* Threads of the OpenMP loops over rows (results do not depend on it). */
+void or_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

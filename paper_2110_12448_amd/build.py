@@ -24,16 +24,43 @@ def sources():
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every HIP source into libpfiso.so (always recompiles)."""
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + FLAGS + ["-I" + os.path.join(ROOT, "include"), "-o", tmp] + sources()
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libpfiso.so")
-    os.replace(tmp, LIB)
+    """Compile every HIP source into libpfiso.so (always recompiles): one
+    hipcc process per source in parallel, then one link."""
+    import shutil
+    import tempfile
+    tmpdir = tempfile.mkdtemp(prefix="pfiso_build_")
+    try:
+        inc = "-I" + os.path.join(ROOT, "include")
+        comp = [f for f in FLAGS if f != "-shared"]
+        procs = []
+        objs = []
+        for src in sources():
+            obj = os.path.join(tmpdir, os.path.basename(src) + ".o")
+            cmd = [HIPCC] + comp + [inc, "-c", "-o", obj, src]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE,
+                                                stderr=subprocess.STDOUT, text=True)))
+            objs.append(obj)
+        failed = []
+        for src, pr in procs:
+            out, _ = pr.communicate()
+            if pr.returncode != 0:
+                failed.append(src)
+                sys.stderr.write(out)
+        if failed:
+            raise RuntimeError("hipcc failed on " + ", ".join(failed))
+        tmp = LIB + ".tmp%d" % os.getpid()
+        cmd = [HIPCC] + FLAGS + ["-o", tmp] + objs
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError("hipcc failed linking libpfiso.so")
+        os.replace(tmp, LIB)
+    finally:
+        shutil.rmtree(tmpdir, ignore_errors=True)
     return LIB
 
 

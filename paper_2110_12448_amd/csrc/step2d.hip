@@ -372,7 +372,19 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
     iter(I1{}, y0 - 1);
     iter(I2{}, y0);
     iter(I3{}, y0 + 1);
-    for (int r = y0 + 2; r <= ye + 1; ++r) iter(I4{}, r);
+    // steady state unrolled by 6, a multiple of every register-rotation
+    // period (3 for the row window and the loads in flight, 2 for alpha_A and
+    // the grain, 1 for the carries), so the rotation costs no register moves
+    int r = y0 + 2;
+    for (; r + 5 <= ye + 1; r += 6) {
+      iter(I4{}, r);
+      iter(I4{}, r + 1);
+      iter(I4{}, r + 2);
+      iter(I4{}, r + 3);
+      iter(I4{}, r + 4);
+      iter(I4{}, r + 5);
+    }
+    for (; r <= ye + 1; ++r) iter(I4{}, r);
     if (kReduce) over_any = __any(over);
   }
 

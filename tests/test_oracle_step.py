@@ -307,3 +307,18 @@ def test_round_f32_mode_is_storage_rounding():
     assert np.array_equal(b.astype(np.float32).astype(np.float64), b)
     d = np.max(np.abs(np.tanh(a / SQ2) - np.tanh(b / SQ2)))
     assert 0 < d < 1e-5
+
+
+def test_thread_count_does_not_change_results():
+    """Rows are independent: one OpenMP thread and all of them give the same
+    bits."""
+    pr = wl.config_small_2d(30.0, n=48, **wl.SCHEMES_2D["S21"])
+    p = oracle.Params.from_problem(pr)
+    n = oracle.num_threads()
+    a = oracle.step(p, pr["psi0"], pr["U0"], pr["grain"], 5)
+    try:
+        oracle.set_num_threads(1)
+        b = oracle.step(p, pr["psi0"], pr["U0"], pr["grain"], 5)
+    finally:
+        oracle.set_num_threads(n)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
