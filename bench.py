@@ -32,7 +32,7 @@ PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector (published)
 # FP32 operations per cell-update of the 2D step as written in step2d.hip
 # (FMA = 2, each transcendental = 1; index math, selects and cross-lane moves
 # not counted); derivation in the design doc.
-ALG_FLOPS_2D = 237
+ALG_FLOPS_2D = 215
 # compulsory bytes per cell-update: read psi, U; write psi, U (FP32)
 ALG_BYTES_2D_F32 = 16
 # FP32 operations per cell-update of the 3D step as written in step3d.hip
@@ -43,7 +43,7 @@ ALG_BYTES_3D_F32 = 17
 # FP32 operations per cell-update of the 2D step under the three schemes of
 # Table 1 (same counting rules; the full current adds three App. B gradients,
 # the two-point faces replace the shell divergences)
-SCHEME_FLOPS_2D = {"S10": 221, "S21": 319, "Sbar21": 237}
+SCHEME_FLOPS_2D = {"S10": 199, "S21": 297, "Sbar21": 215}
 # Table 1: wall time of the whole isothermal run on a Tesla P100 (context)
 PAPER_TABLE1_S = {"S10": 1359.0, "S21": 4612.0, "Sbar21": 3883.0}
 

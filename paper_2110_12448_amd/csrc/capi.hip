@@ -241,6 +241,9 @@ Coef<T> coef_of(const pf_solver *s) {
     c.cT = (T)(1.0 / (2.0 * h2));
     c.cTA = (T)(1.0 / (2.0 * h));
     c.at_eps = (T)(1e-12 * h2);
+    c.ac_eps = (T)(4e-12 * h2);
+    c.an1 = (T)(1.0 + p.eps4);
+    c.an8 = (T)(8.0 * p.eps4);
   } else {
     // L_{1,0,0} = s/h^2, L_{0,1,0} = s/(4h^2), L_{0,0,1} = s/(4h^2)
     c.cL1 = (T)(s->w[0] / h2);

@@ -46,47 +46,46 @@ namespace pf {
 
 namespace {
 
-constexpr float kGradEps = 1e-12f;  // |grad psi|^2 below this: a_s = 1, no torque
-
 template <typename T>
 struct Rot2 {
   T r00, r01, r10, r11;  // crystal -> lab
 };
 
-// a_s for lab gradient (gx, gy) (Eq. anis_function in the cubic form
-// 1 - 3 eps4 + 4 eps4 sum n'^4, n' = R^T n); 1 for a vanishing gradient.
+// Both functions take the gradient in any positive multiple of its true
+// value (g~ = s g): a_s does not depend on the scale and J is homogeneous of
+// degree 1, so J(g~) = s J(g).  g2eps is the guard |g|^2 <= 1e-12 expressed
+// for g~ (1e-12 s^2): at or below it a_s = 1 and J = g~.
+//
+// In 2D the cubic form of Eq. anis_function, a_s = 1 - 3 eps4 + 4 eps4
+// (u^4 + v^4) with (u, v) = R^T g/|g|, equals 1 + eps4 - 8 eps4 u^2 v^2
+// (= 1 + eps4 cos 4(theta - alpha0)).
 template <typename T>
-__device__ __forceinline__ T aniso_a(T gx, T gy, const Rot2<T> &R, const Coef<T> &c) {
+__device__ __forceinline__ T aniso_a(T gx, T gy, T g2eps, const Rot2<T> &R, const Coef<T> &c) {
   T g2 = gx * gx + gy * gy;
-  T r2 = Math<T>::rcp(g2 > T(kGradEps) ? g2 : T(kGradEps));
+  T r2 = Math<T>::rcp(g2 > g2eps ? g2 : g2eps);
   T cx = R.r00 * gx + R.r10 * gy;
   T cy = R.r01 * gx + R.r11 * gy;
-  T cx2 = cx * cx, cy2 = cy * cy;
-  T s4 = (cx2 * cx2 + cy2 * cy2) * (r2 * r2);
-  T a = c.an0 + c.an4 * s4;
-  return g2 > T(kGradEps) ? a : T(1);
+  T w = cx * cy * r2;
+  T a = c.an1 - c.an8 * w * w;
+  return g2 > g2eps ? a : T(1);
 }
 
 // Component `comp` (0: x, 1: y) of the anisotropic flux
-// J = a^2 g + |g|^2 a da/dg at a face with lab gradient g:
-// J = R [ g' (a^2 - 16 eps4 a s4) + 16 eps4 a g'^3 / |g|^2 ],  g' = R^T g.
+// J = a^2 g + |g|^2 a da/dg.  In 2D the second term is a (da/dtheta) g_perp,
+// g_perp = (-gy, gx), with da/dtheta = -16 eps4 u v (u^2 - v^2).
 template <typename T, int comp>
-__device__ __forceinline__ T aniso_flux(T gx, T gy, const Rot2<T> &R, const Coef<T> &c) {
+__device__ __forceinline__ T aniso_flux(T gx, T gy, T g2eps, const Rot2<T> &R,
+                                        const Coef<T> &c) {
   T g2 = gx * gx + gy * gy;
-  T r2 = Math<T>::rcp(g2 > T(kGradEps) ? g2 : T(kGradEps));
+  T r2 = Math<T>::rcp(g2 > g2eps ? g2 : g2eps);
   T cx = R.r00 * gx + R.r10 * gy;
   T cy = R.r01 * gx + R.r11 * gy;
-  T cx2 = cx * cx, cy2 = cy * cy;
-  T s4 = (cx2 * cx2 + cy2 * cy2) * (r2 * r2);
-  T a = c.an0 + c.an4 * s4;
-  T t = c.an16 * a;
-  T base = a * a - t * s4;
-  T tr = t * r2;
-  T jx = cx * (base + tr * cx2);
-  T jy = cy * (base + tr * cy2);
-  T j = comp == 0 ? R.r00 * jx + R.r01 * jy : R.r10 * jx + R.r11 * jy;
+  T w = cx * cy * r2;
+  T a = c.an1 - c.an8 * w * w;
+  T ath = c.an16 * w * ((cx * cx - cy * cy) * r2);  // -da/dtheta
+  T j = comp == 0 ? a * (a * gx + ath * gy) : a * (a * gy - ath * gx);
   T plain = comp == 0 ? gx : gy;
-  return g2 > T(kGradEps) ? j : plain;
+  return g2 > g2eps ? j : plain;
 }
 
 // Logical blocks -> hardware blocks so that each of the 8 XCDs (which take
@@ -203,13 +202,10 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
         pCW2 = from_left(pCW);
       }
 
-      // y face between rows r-1 and r, grain of the lower cell
-      T FyN;
-      {
-        T gyn = (pN - pC) * c.inv_h;
-        T gxt = (pNE + pCE - pNW - pCW) * (T(0.25) * c.inv_h);
-        FyN = aniso_flux<T, 1>(gxt, gyn, rot_of(gC), c);
-      }
+      // y face between rows r-1 and r, grain of the lower cell; face
+      // fluxes are h J (gradients passed as h g)
+      T FyN = aniso_flux<T, 1>(T(0.25) * (pNE + pCE - pNW - pCW), pN - pC, c.at_eps,
+                               rot_of(gC), c);
       if constexpr (P >= 2) {
         // ---------------- psi rate at row m (window rows S, C, N = m-1, m, m+1)
         const int m = r - 1;
@@ -221,14 +217,11 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
         T ex = pCE - pCW, ey = pN - pS;
         T e1 = pNE - pSW, e2 = pSE - pNW;
         T G = c.cG1 * (ex * ex + ey * ey) + c.cG2 * (e1 * e1 + e2 * e2);
-        T hh = T(0.5) * c.inv_h;
-        T ac = aniso_a(ex * hh, ey * hh, R, c);
-        T gxn = dE * c.inv_h;
-        T gyt = (pN + pNE - pS - pSE) * (T(0.25) * c.inv_h);
-        T FxE = aniso_flux<T, 0>(gxn, gyt, R, c);
+        T ac = aniso_a(ex, ey, c.ac_eps, R, c);  // (ex, ey) = 2h g
+        T FxE = aniso_flux<T, 0>(dE, T(0.25) * (pN + pNE - pS - pSE), c.at_eps, R, c);
         T FxW = from_left(FxE);
         T ac2 = ac * ac;
-        T Nn = (FxE - FxW + FyN - FyS) * c.inv_h - ac2 * (s10 * c.cStd);
+        T Nn = (FxE - FxW + FyN - FyS - ac2 * s10) * c.cStd;
         T F1 = T(1), F2 = uC;
         if (kFrozen) {
           T zeta = (T)ghost_near(m, ny, a.bcy) * c.h + off;
