@@ -152,6 +152,16 @@ int pf_create(const pf_params *p, const pf_init *init, void *workspace,
  * waiting.  Non-finite values surface at the next pf_tip_state. */
 int pf_step(pf_solver *s, int64_t nsteps);
 
+/* Enqueue nsteps steps of the solute-diffusion part of Eq. PF_b alone, with
+ * psi held fixed (d psi/dt = 0, so the anti-trapping current and the source
+ * vanish): U <- U + dt D~ D_{s1,s2}(1 - phi, U) / (1 + k - (1-k) phi) on the
+ * shell divergence of the solver's weights (Sec. 4.1), psi copied to the next
+ * buffer.  Each step reads and writes the same arrays as pf_step (16 bytes per
+ * cell in FP32) with a fraction of its arithmetic, so it shows the
+ * memory-bound regime of the same layout.  The moving-frame rule applies as in
+ * pf_step.  2D only and shell divergences only (PF_ERR_ARG otherwise). */
+int pf_step_diffusion(pf_solver *s, int64_t nsteps);
+
 /* Wait for the solver's stream. */
 int pf_synchronize(pf_solver *s);
 

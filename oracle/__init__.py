@@ -53,6 +53,7 @@ class _Params(C.Structure):
         ("bc", C.c_int32 * 3), ("frame", C.c_int32), ("shift_row", C.c_int32),
         ("n_grains", C.c_int32), ("rot", C.POINTER(C.c_double)),
         ("round_f32", C.c_int32), ("antitrapping", C.c_int32), ("two_point", C.c_int32),
+        ("frozen_psi", C.c_int32),
     ]
 
 
@@ -121,6 +122,7 @@ class Params:
     round_f32: int = 0
     antitrapping: int = 0
     two_point: int = 0
+    frozen_psi: int = 0
     _keep: list = field(default_factory=list, repr=False)
 
     @classmethod
@@ -151,6 +153,7 @@ class Params:
         cp.round_f32 = int(self.round_f32)
         cp.antitrapping = int(self.antitrapping)
         cp.two_point = int(self.two_point)
+        cp.frozen_psi = int(self.frozen_psi)
         return cp
 
 

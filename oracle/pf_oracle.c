@@ -575,7 +575,7 @@ void or_rates(const or_params *p, const double *psi, const double *U,
     double a2 = ac[c] * ac[c];
     double rhs = a2 * (L[c] - SQRT2 * ph * G[c]) + N[c] +
                  SQRT2 * (ph - p->lambda * (1.0 - ph * ph) * F2);
-    rate_psi[c] = rhs / (F1 * a2);
+    rate_psi[c] = p->frozen_psi ? 0.0 : rhs / (F1 * a2);
     aD[c] = 1.0 - ph;
     aA[c] = (1.0 + (1.0 - k) * U[c]) * (1.0 - ph * ph) * rate_psi[c] / 2.0;
   }

@@ -48,6 +48,9 @@ typedef struct or_params {
                                current of Eq. Anti_convention (2D only) */
   int32_t two_point;        /* 1: standard <10> divergences with two-point
                                face averages of alpha (2D scheme S_{1,0}) */
+  int32_t frozen_psi;       /* 1: psi held fixed (d psi/dt = 0), U evolves by
+                               Eq. PF_b alone: solute diffusion through a
+                               frozen phase field */
 } or_params;
 
 typedef struct or_tip {

@@ -11,9 +11,12 @@ ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libpfiso.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-# Packed FP32 VALU forms are switched off for every device pass.
+# Packed FP32 VALU forms are switched off for every device pass.  Multiplies
+# and adds are fused only within one source expression (-ffp-contract=on), so
+# every inlined copy of an expression rounds the same way: a row computed in
+# a segment's prologue is bitwise the row computed in the steady state.
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]

@@ -33,10 +33,14 @@ int fail(int code, const std::string &msg) {
 constexpr double kA2 = 47.0 / 75.0;
 // Rows per wave segment in 2D: about 4.5 waves per SIMD on the 1024 SIMDs of
 // an MI355X when the lattice is small (short segments cost a 2-row psi
-// recompute each), up to 32 rows when there is work to spare (sweep on
-// 1024x2048 and 8192x8192 lattices).
+// recompute each), up to 32 rows when there is work to spare; 6 rows when
+// 8-row segments would leave fewer than 2 waves per SIMD (sweeps on 781^2,
+// 1024x2048 and 8192x8192 lattices).  Batched members keep at least 8 rows:
+// the batch fills the chip by itself.
+constexpr int kMinSegBatch2D = 8;
 int default_seg2d(int nx, int ny) {
   long long strips = (nx + 59) / 60;
+  if (strips * ((ny + 7) / 8) < 2048) return 6;
   long long seg = strips * ny / 4608;
   return (int)(seg < 8 ? 8 : (seg > 32 ? 32 : seg));
 }
@@ -289,10 +293,10 @@ int upload(pf_solver *s, const pf_init *init) {
 
 // Argument block of the 2D step of solver s (pointers set per launch).
 template <typename T>
-Geom2D fill2d(pf_solver *s, Step2DArgs<T> &a) {
+Geom2D fill2d(pf_solver *s, Step2DArgs<T> &a, int min_seg = 1) {
   const pf_params &p = s->p;
   memset(&a, 0, sizeof(a));
-  Geom2D g = geom2d(p.nx, p.ny, s->seg);
+  Geom2D g = geom2d(p.nx, p.ny, std::max(s->seg, min_seg));
   a.grain = p.n_grains > 1 ? reinterpret_cast<const int8_t *>(s->ws + s->L.grain) : nullptr;
   a.rot = field<T>(s, s->L.rot);
   a.r00 = (T)s->rot[0]; a.r01 = (T)s->rot[1]; a.r10 = (T)s->rot[3]; a.r11 = (T)s->rot[4];
@@ -305,7 +309,7 @@ Geom2D fill2d(pf_solver *s, Step2DArgs<T> &a) {
 }
 
 template <typename T>
-int step_impl(pf_solver *s, long long nsteps) {
+int step_impl(pf_solver *s, long long nsteps, bool diffusion_only = false) {
   const pf_params &p = s->p;
   const bool frozen = p.lT > 0.0;
   const bool reduce = p.frame != 0;
@@ -317,8 +321,9 @@ int step_impl(pf_solver *s, long long nsteps) {
     Geom2D g = fill2d<T>(s, a);
     (void)c;
     const bool two = p.divergence == PF_DIV_TWO_POINT;
-    const int at = p.antitrapping == PF_AT_FULL ? (two ? kAtFullTwoPoint : kAtFullShells)
-                                                : (two ? kAtApproxTwoPoint : kAtApproxShells);
+    const int at = diffusion_only ? kAtDiffusionOnly
+                   : p.antitrapping == PF_AT_FULL ? (two ? kAtFullTwoPoint : kAtFullShells)
+                                                  : (two ? kAtApproxTwoPoint : kAtApproxShells);
     for (long long i = 0; i < nsteps; ++i) {
       a.psi_in = field<T>(s, s->L.psi[s->cur]);
       a.U_in = field<T>(s, s->L.U[s->cur]);
@@ -445,7 +450,7 @@ int batch_build(pf_batch *b) {
     pf_solver *s = b->s[i];
     BatchSolve2D<T> &e = tab[i];
     memset(&e, 0, sizeof(e));
-    Geom2D g = fill2d<T>(s, e.a);
+    Geom2D g = fill2d<T>(s, e.a, kMinSegBatch2D);
     for (int k = 0; k < 2; ++k) {
       e.psi[k] = field<T>(s, s->L.psi[k]);
       e.U[k] = field<T>(s, s->L.U[k]);
@@ -717,6 +722,16 @@ int pf_step(pf_solver *s, int64_t nsteps) {
   if (!s) return fail(PF_ERR_ARG, "solver is NULL");
   if (nsteps < 0) return fail(PF_ERR_ARG, "nsteps must be >= 0");
   return s->p.precision == PF_F64 ? step_impl<double>(s, nsteps) : step_impl<float>(s, nsteps);
+}
+
+int pf_step_diffusion(pf_solver *s, int64_t nsteps) {
+  if (!s) return fail(PF_ERR_ARG, "solver is NULL");
+  if (nsteps < 0) return fail(PF_ERR_ARG, "nsteps must be >= 0");
+  if (s->p.dim != 2) return fail(PF_ERR_ARG, "the diffusion-only step is 2D only");
+  if (s->p.divergence != PF_DIV_SHELLS)
+    return fail(PF_ERR_ARG, "the diffusion-only step uses the shell divergence");
+  return s->p.precision == PF_F64 ? step_impl<double>(s, nsteps, true)
+                                  : step_impl<float>(s, nsteps, true);
 }
 
 int pf_synchronize(pf_solver *s) {

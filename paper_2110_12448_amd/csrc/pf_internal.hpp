@@ -139,6 +139,7 @@ enum At2D : int {
   kAtFullShells = 1,      // full current, App. B |grad psi| at the flux points (S_{2,1})
   kAtFullTwoPoint = 2,    // full current, two-point <10> faces (S_{1,0})
   kAtApproxTwoPoint = 3,  // approximated current, two-point <10> faces
+  kAtDiffusionOnly = 4,   // psi held, U by D~ div[(1 - phi) grad U] alone (shells)
 };
 
 template <typename T>

@@ -37,7 +37,10 @@
 //                      of the two cells as face alpha, the full current with
 //                      the face gradient from the normal difference and the
 //                      four-point tangential difference (S_{1,0});
-//   kAtApproxTwoPoint  the same faces with the approximated current.
+//   kAtApproxTwoPoint  the same faces with the approximated current;
+//   kAtDiffusionOnly   psi held (copied), U advanced by the diffusion term of
+//                      Eq. PF_b alone on the shell divergence: the same bytes
+//                      per cell with a fraction of the arithmetic.
 #include <type_traits>
 
 #include "pf_device.hpp"
@@ -101,6 +104,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 template <typename T, bool kFrozen, bool kReduce, bool kMulti, int kAT>
 __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb) {
   constexpr bool kTwoPoint = kAT == kAtFullTwoPoint || kAT == kAtApproxTwoPoint;
+  constexpr bool kDiff = kAT == kAtDiffusionOnly;
   using M = Math<T>;
   const Coef<T> &c = a.c;
   const int lane = threadIdx.x & 63;
@@ -204,9 +208,21 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
 
       // y face between rows r-1 and r, grain of the lower cell; face
       // fluxes are h J (gradients passed as h g)
-      T FyN = aniso_flux<T, 1>(T(0.25) * (pNE + pCE - pNW - pCW), pN - pC, c.at_eps,
-                               rot_of(gC), c);
-      if constexpr (P >= 2) {
+      T FyN = T(0);
+      if constexpr (!kDiff)
+        FyN = aniso_flux<T, 1>(T(0.25) * (pNE + pCE - pNW - pCW), pN - pC, c.at_eps, rot_of(gC),
+                               c);
+      if constexpr (P >= 2 && kDiff) {
+        // psi is held: copy row m and take the frame decision on it
+        const int m = r - 1;
+        if (P >= 3 && m < ye) {
+          if (out_lane) a.psi_out[(size_t)m * (size_t)nx + (size_t)x] = pC;
+          if (kReduce && out_lane && m <= ny - 2 && fC >= T(0) && fN < T(0)) {
+            double fc = (double)fC, fn = (double)fN;
+            over |= ((double)m + fc / (fc - fn)) * a.hd >= ythr;
+          }
+        }
+      } else if constexpr (P >= 2) {
         // ---------------- psi rate at row m (window rows S, C, N = m-1, m, m+1)
         const int m = r - 1;
         const Rot2<T> R = rot_of(gC);
@@ -293,12 +309,16 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
         T fND = (aq + aq1 + PD + PDW) * (uC - uS);
         T d1D = PD * (uNE - uS), d2D = PDW * (uNW - uS);
 
-        T bE = from_right(aAS), bNE = from_right(aAC);
-        T PA = (aAS + bE + aAC + bNE) * T(0.25);
-        T PAW = from_left(PA);
-        T fEA = (aAS + bE + PA + cPA) * (pSE - pS);
-        T fNA = (aAS + aAC + PA + PAW) * (pC - pS);
-        T d1A = PA * (pCE - pS), d2A = PAW * (pCW - pS);
+        T PA = T(0), fEA = T(0), fNA = T(0), d1A = T(0), d2A = T(0);
+        if constexpr (!kDiff) {
+          T bE = from_right(aAS), bNE = from_right(aAC);
+          PA = (aAS + bE + aAC + bNE) * T(0.25);
+          T PAW = from_left(PA);
+          fEA = (aAS + bE + PA + cPA) * (pSE - pS);
+          fNA = (aAS + aAC + PA + PAW) * (pC - pS);
+          d1A = PA * (pCE - pS);
+          d2A = PAW * (pCW - pS);
+        }
 
         if constexpr (kAT == kAtFullShells) {
           // App. B gradients (times h) at the north face (q+1/2), the north-east
@@ -349,7 +369,9 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
           T divD = c.cD1 * (fED + fWD + fND - cND) + c.cD2 * (d1D + d2D + swD + seD);
           T divA = (kF ? c.cA1 : c.cD1) * (fEA + fWA + fNA - cNA) +
                    (kF ? c.cA2 : c.cD2) * (d1A + d2A + swA + seA);
-          T rU = (c.D * divD + divA + sq2 * aAS) * M::rcp(T(1) + c.k - c.omk * fS);
+          // the held psi has no anti-trapping current and no source
+          T rU = (kDiff ? c.D * divD : c.D * divD + divA + sq2 * aAS) *
+                 M::rcp(T(1) + c.k - c.omk * fS);
           if (out_lane) a.U_out[(size_t)q * (size_t)nx + (size_t)x] = uS + c.dt * rU;
         }
         cND = fND; c1D = d1D; c2D = d2D; cPD = PD;
@@ -474,6 +496,9 @@ hipError_t launch_step2d(const Step2DArgs<T> &a, const Geom2D &g, bool frozen, b
     case kAtFullTwoPoint: launch_step2d_at<T, kAtFullTwoPoint>(a, g, frozen, reduce, multi, st); break;
     case kAtApproxTwoPoint:
       launch_step2d_at<T, kAtApproxTwoPoint>(a, g, frozen, reduce, multi, st);
+      break;
+    case kAtDiffusionOnly:
+      launch_step2d_at<T, kAtDiffusionOnly>(a, g, frozen, reduce, multi, st);
       break;
     default: return hipErrorInvalidValue;
   }

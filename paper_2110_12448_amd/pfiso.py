@@ -34,7 +34,7 @@ PF_AT_APPROX, PF_AT_FULL = 0, 1
 PF_DIV_SHELLS, PF_DIV_TWO_POINT = 0, 1
 
 EXPORTED = ("pf_version", "pf_last_error", "pf_stable_dt", "pf_workspace_bytes", "pf_create",
-            "pf_step", "pf_synchronize", "pf_read_fields", "pf_tip_state", "pf_device_fields",
+            "pf_step", "pf_step_diffusion", "pf_synchronize", "pf_read_fields", "pf_tip_state", "pf_device_fields",
             "pf_frame_state", "pf_tune", "pf_destroy", "pf_batch_create", "pf_batch_step",
             "pf_batch_use_graph", "pf_batch_destroy")
 
@@ -89,6 +89,7 @@ def load(path: str = LIB_PATH):
     lib.pf_create.argtypes = [P(pf_params), P(pf_init), C.c_void_p, C.c_size_t, C.c_void_p,
                               P(C.c_void_p)]
     lib.pf_step.argtypes = [C.c_void_p, C.c_int64]
+    lib.pf_step_diffusion.argtypes = [C.c_void_p, C.c_int64]
     lib.pf_synchronize.argtypes = [C.c_void_p]
     lib.pf_read_fields.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double), P(C.c_double),
                                    P(C.c_int8)]
@@ -184,6 +185,10 @@ class Solver:
 
     def step(self, nsteps: int = 1):
         _check(load().pf_step(self.handle, int(nsteps)))
+
+    def step_diffusion(self, nsteps: int = 1):
+        """U by the diffusion term of Eq. PF_b alone, psi held (pf_step_diffusion)."""
+        _check(load().pf_step_diffusion(self.handle, int(nsteps)))
 
     def synchronize(self):
         _check(load().pf_synchronize(self.handle))

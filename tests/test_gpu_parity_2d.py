@@ -184,3 +184,23 @@ def test_nonfinite_detected():
         s.tip_state()
     assert e.value.code == pf.PF_ERR_NONFINITE
     s.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("kw", [{}, wl.SCHEMES_2D["S21"], wl.SCHEMES_2D["S10"]])
+def test_segment_length_does_not_change_results(prec, kw):
+    """Rows per wave segment (pf_tune) only move the recomputed halo rows: the
+    results are bitwise the same for every segment length, ragged or not."""
+    pf = _pf()
+    pr = wl.config_small_2d(30.0, n=150, frame=1, shift_row=20, **kw)
+    out = []
+    for seg in (4, 6, 8, 13, 32):
+        s = pf.Solver(pr, precision=prec)
+        s.tune(seg, 1)
+        s.step(40)
+        phi, U, psi, _ = s.read_fields()
+        out.append((psi, U, s.frame_state()[0]))
+        s.close()
+    for psi, U, shift in out[1:]:
+        assert np.array_equal(psi, out[0][0]) and np.array_equal(U, out[0][1])
+        assert shift == out[0][2]
