@@ -37,7 +37,7 @@ ALG_FLOPS_2D = 215
 ALG_BYTES_2D_F32 = 16
 # FP32 operations per cell-update of the 3D step as written in step3d.hip
 # (same counting rules; derivation in the design doc)
-ALG_FLOPS_3D = 1000
+ALG_FLOPS_3D = 592
 # read psi, U, the int8 grain; write psi, U
 ALG_BYTES_3D_F32 = 17
 # FP32 operations per cell-update of the 2D step under the three schemes of

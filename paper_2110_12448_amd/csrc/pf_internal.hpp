@@ -59,6 +59,8 @@ struct Coef {
   T at_eps;         // 1e-12 h^2: the |g|^2 <= 1e-12 guard for h g (face gradients, 2D)
   T ac_eps;         // 4e-12 h^2: the same guard for 2h g (centre differences, 2D)
   T an1, an8;       // 1 + eps4, 8 eps4 (2D a_s = 1 + eps4 - 8 eps4 u^2 v^2)
+  T k1a, k1b;       // cD1/4, cD1/16: <100> link alpha weights times the shell coefficient (3D)
+  T k2a, k2b;       // 3 cD2/16, cD2/32: the same for <110> links (3D)
 };
 
 template <typename T>

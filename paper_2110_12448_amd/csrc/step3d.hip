@@ -18,12 +18,18 @@
 // each side), `ztile` output z-rows and a segment of `seg` y-rows.  It runs
 // ztile + 2 waves, one per z-row including a ring row on each side (the ring
 // waves also load the outer psi halo rows), which march up the segment in
-// lock-step.  Each iteration publishes the newest psi, U, phi row in LDS rings
-// of 5 rows, then (barrier) computes the psi rate of the row below from the
-// LDS 3x3x3 neighbourhood and publishes alpha_A, then (barrier) the output
-// waves update U two rows below from the 3x3x3 neighbourhoods of alpha_D =
-// 1 - phi, alpha_A, U and psi.  No-flux walls: psi, U and phi are read through
-// the mirror map, alpha_A of a mirrored cell is replaced by its image.
+// lock-step.  Each iteration publishes the newest psi, U and D~(1 - phi) row
+// in LDS rings of 5 rows, then (barrier) computes the psi rate of the row
+// below from the LDS 3x3x3 neighbourhood and publishes alpha_A, then
+// (barrier) evaluates the divergence links of the row below that.  Every
+// link is evaluated once: a cell owns the 9 links towards +x, +y or +z and
+// takes the other 9 with the opposite sign from the lane to its left, from
+// the row below (register carries) and, for links to the z-rows below and
+// the yz links to the row below, from an exchange buffer in which each wave
+// publishes two sums per lane and row.  A row's U is therefore finished one
+// iteration later, after the next barriers.  No-flux walls: psi, U and phi
+// are read through the mirror map, and every field beyond a wall is read at
+// its image (alpha_A of a mirrored cell included).
 #include <type_traits>
 
 #include "pf_device.hpp"
@@ -79,92 +85,22 @@ __host__ __device__ constexpr int nb(int dx, int dy, int dz) {
 
 constexpr int kRS = 66;  // LDS row stride: lane l at l + 1, pads at 0 and 65
 
-// Generalised divergence sum_links abar (beta_d - beta_0) over the three
-// shells for one cell, from its 3x3x3 alpha and beta neighbourhoods; returns
-// cD1 S100 + cD2 S110 + cD3 S111.
-template <typename T, bool kShell3>
-__device__ __forceinline__ T divergence27(const T (&A)[27], const T (&B)[27], const Coef<T> &c) {
-  const T b0 = B[nb(0, 0, 0)];
-  // <100>: abar = 1/4 (alpha_0 + alpha_d) + 1/16 sum over the 4 tangential
-  // offsets t of (alpha_t + alpha_{d+t})
-  T s100 = T(0);
-#pragma unroll
-  for (int ax = 0; ax < 3; ++ax) {
-#pragma unroll
-    for (int sg = -1; sg <= 1; sg += 2) {
-      int d[3] = {0, 0, 0};
-      d[ax] = sg;
-      T near = A[nb(0, 0, 0)] + A[nb(d[0], d[1], d[2])];
-      T far = T(0);
-#pragma unroll
-      for (int tx = 0; tx < 3; ++tx) {
-        if (tx == ax) continue;
-#pragma unroll
-        for (int ts = -1; ts <= 1; ts += 2) {
-          int t[3] = {0, 0, 0};
-          t[tx] = ts;
-          far += A[nb(t[0], t[1], t[2])] + A[nb(d[0] + t[0], d[1] + t[1], d[2] + t[2])];
-        }
-      }
-      T abar = T(0.25) * near + T(0.0625) * far;
-      s100 += abar * (B[nb(d[0], d[1], d[2])] - b0);
-    }
-  }
-  // <110>: abar = 3/16 (in-plane plaquette) + 1/32 (the plaquettes above and
-  // below along the third axis)
-  T s110 = T(0);
-#pragma unroll
-  for (int a1 = 0; a1 < 3; ++a1) {
-#pragma unroll
-    for (int a2 = a1 + 1; a2 < 3; ++a2) {
-      const int am = 3 - a1 - a2;
-#pragma unroll
-      for (int s1 = -1; s1 <= 1; s1 += 2) {
-#pragma unroll
-        for (int s2 = -1; s2 <= 1; s2 += 2) {
-          int e1[3] = {0, 0, 0}, e2[3] = {0, 0, 0}, d[3] = {0, 0, 0};
-          e1[a1] = s1;
-          e2[a2] = s2;
-          d[a1] = s1;
-          d[a2] = s2;
-          T in = A[nb(0, 0, 0)] + A[nb(e1[0], e1[1], e1[2])] + A[nb(e2[0], e2[1], e2[2])] +
-                 A[nb(d[0], d[1], d[2])];
-          T out = T(0);
-#pragma unroll
-          for (int sm = -1; sm <= 1; sm += 2) {
-            int m[3] = {0, 0, 0};
-            m[am] = sm;
-            out += A[nb(m[0], m[1], m[2])] + A[nb(e1[0] + m[0], e1[1] + m[1], e1[2] + m[2])] +
-                   A[nb(e2[0] + m[0], e2[1] + m[1], e2[2] + m[2])] +
-                   A[nb(d[0] + m[0], d[1] + m[1], d[2] + m[2])];
-          }
-          T abar = T(0.1875) * in + T(0.03125) * out;
-          s110 += abar * (B[nb(d[0], d[1], d[2])] - b0);
-        }
-      }
-    }
-  }
-  T res = c.cD1 * s100 + c.cD2 * s110;
-  if constexpr (kShell3) {
-    // <111>: abar = mean of the 8 corners of the cube spanned by 0 and d
-    T s111 = T(0);
-#pragma unroll
-    for (int sx = -1; sx <= 1; sx += 2)
-#pragma unroll
-      for (int sy = -1; sy <= 1; sy += 2)
-#pragma unroll
-        for (int sz = -1; sz <= 1; sz += 2) {
-          T cube = A[nb(0, 0, 0)] + A[nb(sx, 0, 0)] + A[nb(0, sy, 0)] + A[nb(0, 0, sz)] +
-                   A[nb(sx, sy, 0)] + A[nb(sx, 0, sz)] + A[nb(0, sy, sz)] + A[nb(sx, sy, sz)];
-          s111 += T(0.125) * cube * (B[nb(sx, sy, sz)] - b0);
-        }
-    res += c.cD3 * s111;
-  }
-  return res;
-}
+// alpha averages of the links a cell owns, times their shell coefficient
+// (Eqs. divergence_100, divergence_110): <100> links abar = P(0) + P(d) with
+// P = alpha/4 + (sum of the 4 neighbours across the link axis)/16; <110>
+// links abar = 3/16 (in-plane plaquette) + 1/32 (the two plaquettes beside
+// it along the third axis).  Py1 is P_y of the cell one row up, carried.
+template <typename T>
+struct Abar9 {
+  T E, N, Up, NE, NW, EU, WU, NU, ND, Py1;
+};
+template <typename T>
+struct Diff9 {
+  T E, N, Up, NE, NW, EU, WU, NU, ND;
+};
 
 // FP32 workgroups run up to 10 waves (ztile <= 8); FP64 ones up to 4
-// (ztile <= 2, bounded by LDS), which leaves them the whole register file.
+// (ztile <= 2), which leaves them the whole register file.
 template <typename T>
 constexpr int max_threads3d() { return sizeof(T) == 8 ? 256 : 640; }
 
@@ -174,12 +110,13 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
   const Coef<T> &c = a.c;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *sm = reinterpret_cast<T *>(smem_raw);
-  const int Z = a.ztile, NZR = Z + 4;
+  const int Z = a.ztile, NZR = Z + 4, NW = Z + 2;
   const int SLOT = NZR * kRS;
   T *psiL = sm;              // 5 row slots each
   T *UL = psiL + 5 * SLOT;
-  T *phL = UL + 5 * SLOT;
-  T *aAL = phL + 5 * SLOT;
+  T *adL = UL + 5 * SLOT;    // alpha_D = D~ (1 - phi)
+  T *aAL = adL + 5 * SLOT;   // alpha_A
+  T *XL = aAL + 5 * SLOT;    // link exchange [row parity][to above, to below][wave][lane]
 
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const int lane = threadIdx.x & 63;
@@ -229,21 +166,42 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
     for (int i = 0; i < 9; ++i) R.m[i] = q[i];
     return R;
   };
-  // LDS element of field F at row slot s, z index zz, lane offset dx
+  // LDS element of field F at row slot s, z layer zz, lane offset dx
   auto L = [&](const T *F, int s, int zz, int dx) -> T {
     return F[(s * NZR + zz) * kRS + lane + 1 + dx];
   };
 
-  // z index of the neighbour below / above for the divergence: a mirrored
-  // (no-flux) neighbour is the cell itself
-  const int ziD = (a.bcz == PF_BC_NOFLUX && z == 0) ? zi : zi - 1;
-  const int ziU = (a.bcz == PF_BC_NOFLUX && z == nz - 1) ? zi : zi + 1;
+  // Divergence neighbourhoods: a z-row or y-row beyond a no-flux wall is read
+  // as its mirror image (alpha_A included, which the ring waves cannot
+  // produce for a mirrored row).  Layers are clamped to the LDS tile: only
+  // waves whose results are unused can reach the clamp.
+  auto zlayer = [&](int zz) -> int {
+    if (a.bcz == PF_BC_NOFLUX) {
+      if (zz < 0) zz = -zz - 1;
+      else if (zz >= nz) zz = 2 * nz - 1 - zz;
+    }
+    return min(max(zz - z0 + 2, 0), NZR - 1);
+  };
+  const int zl[3] = {zlayer(z - 1), zlayer(z), zlayer(z + 1)};
+  auto yslot = [&](int j) {
+    if (a.bcy == PF_BC_NOFLUX) {
+      if (j < 0) j = -j - 1;
+      else if (j >= ny) j = 2 * ny - 1 - j;
+    }
+    return slot5(j);
+  };
 
   // own-row window (rows r-2, r-1, r) and carries
   T pS = 0, pC = 0, pN = 0, uS = 0, uC = 0, uN = 0, fS = 0, fC = 0, fN = 0;
   T aAown[3] = {0, 0, 0};  // alpha_A of own cell at rows m-1, m (index by m mod 3)
   T FyS = 0;               // y face flux below row r-1
   int gC = 0, gN = 0;
+  // shared divergence links: P_y of the next row (fields D, A), the south
+  // links of the row (N, NE, NW of the row below), this wave's NU and ND of
+  // the row below (sent to the neighbouring waves one row late), and the row
+  // waiting for its neighbours' links (U, the own part of the update, 1/den)
+  T PyD = 0, PyA = 0, southSum = 0, NUprev = 0, NDprev = 0;
+  T waitU = 0, waitBase = 0, waitDen = 0;
 
   T nxt_p, nxt_u, nxt_h = 0;
   int nxt_g = 0;
@@ -254,6 +212,18 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
     if (ring) nxt_h = a.psi_in[pzh + ro];
     if (kMulti) nxt_g = a.grain[pz + ro];
   }
+
+  // U of the waiting row qf from its own part and the neighbours' links
+  // (output waves only: their neighbours w - 1 and w + 1 exist in the tile)
+  auto finalize = [&](int qf) {
+    if (!out_wave) return;
+    const int par = qf & 1;
+    const T below = XL[((par * 2 + 0) * NW + (w - 1)) * 64 + lane];
+    const T above = XL[((par * 2 + 1) * NW + (w + 1)) * 64 + lane];
+    if (out_lane)
+      a.U_out[pz + (size_t)qf * nx - (size_t)gx + (size_t)x] =
+          waitU + c.dt * waitDen * (waitBase - below - above);
+  };
 
   auto iter = [&](auto phase, int r) {
     constexpr int P = decltype(phase)::value;
@@ -274,7 +244,7 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
       const int o = (sN * NZR + zi) * kRS + lane + 1;
       psiL[o] = pN;
       UL[o] = uN;
-      phL[o] = fN;
+      adL[o] = c.D * (T(1) - fN);
       if (ring) psiL[(sN * NZR + zih) * kRS + lane + 1] = hN;
     }
     __syncthreads();
@@ -396,47 +366,130 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
     __syncthreads();
 
     if constexpr (P >= 3) {
-      // ---------------- phase C: U update at row q = m - 1 (output waves)
+      // ---------------- phase C: the links this wave owns at row q = m - 1
+      // (P == 3: only those towards row q+1, which the first U row needs)
       const int q = m - 1;
-      if (P == 4 && out_wave) {
-        // rows of the neighbourhood; a mirrored (no-flux) row is the row itself
-        const int syq[3] = {(a.bcy == PF_BC_NOFLUX && q == 0) ? slot5(q) : slot5(q - 1), slot5(q),
-                            (a.bcy == PF_BC_NOFLUX && q == ny - 1) ? slot5(q) : slot5(q + 1)};
-        const int zq[3] = {ziD, zi, ziU};
-        // alpha_A of a mirrored (no-flux) row is its image's value
-        const bool fixS = (a.bcy == PF_BC_NOFLUX && q == 0);
-        const bool fixN = (a.bcy == PF_BC_NOFLUX && q == ny - 1);
-        (void)fixS;
-        (void)fixN;
-        T A[27], B[27];
-        // field D: alpha = 1 - phi, beta = U
-#pragma unroll
-        for (int dz = -1; dz <= 1; ++dz)
-#pragma unroll
-          for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-            for (int dx = -1; dx <= 1; ++dx) {
-              A[nb(dx, dy, dz)] = T(1) - L(phL, syq[dy + 1], zq[dz + 1], dx);
-              const int sh = (dx != 0) + (dy != 0) + (dz != 0);
-              if (sh < 3 || kShell3) B[nb(dx, dy, dz)] = L(UL, syq[dy + 1], zq[dz + 1], dx);
-            }
-        T divD = divergence27<T, kShell3>(A, B, c);
-        // field A: alpha = alpha_A, beta = psi
-#pragma unroll
-        for (int dz = -1; dz <= 1; ++dz)
-#pragma unroll
-          for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-            for (int dx = -1; dx <= 1; ++dx) {
-              A[nb(dx, dy, dz)] = L(aAL, syq[dy + 1], zq[dz + 1], dx);
-              const int sh = (dx != 0) + (dy != 0) + (dz != 0);
-              if (sh < 3 || kShell3) B[nb(dx, dy, dz)] = L(psiL, syq[dy + 1], zq[dz + 1], dx);
-            }
-        T divA = divergence27<T, kShell3>(A, B, c);
-        const T aAq = aAown[(q + 3) % 3];
-        T rU = (c.D * divD + divA + sq2 * aAq) * M::rcp(T(1) + c.k - c.omk * fS);
-        if (out_lane) a.U_out[pz + (size_t)q * nx - (size_t)gx + (size_t)x] = uS + c.dt * rU;
+      const int sl[3] = {yslot(q - 1), yslot(q), yslot(q + 1)};
+      auto rd = [&](const T *F, int dy, int dz, int dx) -> T {
+        return F[(sl[dy + 1] * NZR + zl[dz + 1]) * kRS + lane + 1 + dx];
+      };
+      constexpr bool kFull = P == 4;
+      auto abars = [&](const T *AL, T Pyq) -> Abar9<T> {
+        Abar9<T> o;
+        const T a00 = rd(AL, 0, 0, 0), a10 = rd(AL, 1, 0, 0);
+        const T a0m = rd(AL, 0, -1, 0), a0p = rd(AL, 0, 1, 0);
+        const T a1m = rd(AL, 1, -1, 0), a1p = rd(AL, 1, 1, 0);
+        o.Py1 = c.k1a * a10 + c.k1b * (rd(AL, 1, 0, -1) + rd(AL, 1, 0, 1) + a1m + a1p);
+        o.N = Pyq + o.Py1;
+        // xy plaquettes {x, x+1} x {q, q+1} at z-1, z, z+1
+        const T cm = a0m + a1m, c0 = a00 + a10, cp = a0p + a1p;
+        const T Xm = cm + from_right(cm), X0 = c0 + from_right(c0), Xp = cp + from_right(cp);
+        o.NE = c.k2a * X0 + c.k2b * (Xm + Xp);
+        o.NW = from_left(o.NE);
+        // yz plaquettes {q, q+1} x {z, z+1} (NU) and {z-1, z} (ND) at x-1, x, x+1
+        const T S = c0 + cp, Sd = cm + c0;
+        o.NU = c.k2a * S + c.k2b * (from_left(S) + from_right(S));
+        o.ND = c.k2a * Sd + c.k2b * (from_left(Sd) + from_right(Sd));
+        if constexpr (kFull) {
+          const T am0 = rd(AL, -1, 0, 0), am1 = rd(AL, -1, 1, 0);
+          const T Px = c.k1a * a00 + c.k1b * (am0 + a10 + a0m + a0p);
+          o.E = Px + from_right(Px);
+          const T Pz0 = c.k1a * a00 + c.k1b * (rd(AL, 0, 0, -1) + rd(AL, 0, 0, 1) + am0 + a10);
+          const T Pz1 = c.k1a * a0p + c.k1b * (rd(AL, 0, 1, -1) + rd(AL, 0, 1, 1) + am1 + a1p);
+          o.Up = Pz0 + Pz1;
+          // xz plaquettes {x, x+1} x {z, z+1} at q-1, q, q+1
+          const T ym = am0 + am1, y0s = a00 + a0p, yp = a10 + a1p;
+          const T Ym = ym + from_right(ym), Y0 = y0s + from_right(y0s), Yp = yp + from_right(yp);
+          o.EU = c.k2a * Y0 + c.k2b * (Ym + Yp);
+          o.WU = from_left(o.EU);
+        } else {
+          o.E = o.Up = o.EU = o.WU = T(0);
+        }
+        return o;
+      };
+      auto diffs = [&](const T *BL) -> Diff9<T> {
+        Diff9<T> o;
+        const T b0 = rd(BL, 0, 0, 0);
+        o.N = rd(BL, 1, 0, 0) - b0;
+        o.NE = rd(BL, 1, 0, 1) - b0;
+        o.NW = rd(BL, 1, 0, -1) - b0;
+        o.NU = rd(BL, 1, 1, 0) - b0;
+        o.ND = rd(BL, 1, -1, 0) - b0;
+        if constexpr (kFull) {
+          o.E = rd(BL, 0, 0, 1) - b0;
+          o.Up = rd(BL, 0, 1, 0) - b0;
+          o.EU = rd(BL, 0, 1, 1) - b0;
+          o.WU = rd(BL, 0, 1, -1) - b0;
+        } else {
+          o.E = o.Up = o.EU = o.WU = T(0);
+        }
+        return o;
+      };
+      // P_y of row q itself: carried from the row below except at the start
+      auto py_here = [&](const T *AL) -> T {
+        return c.k1a * rd(AL, 0, 0, 0) +
+               c.k1b * (rd(AL, 0, 0, -1) + rd(AL, 0, 0, 1) + rd(AL, 0, -1, 0) + rd(AL, 0, 1, 0));
+      };
+      if constexpr (!kFull) {
+        PyD = py_here(adL);
+        PyA = py_here(aAL);
       }
+      const Abar9<T> bD = abars(adL, PyD), bA = abars(aAL, PyA);
+      const Diff9<T> dU = diffs(UL), dP = diffs(psiL);
+      PyD = bD.Py1;
+      PyA = bA.Py1;
+      // link values: D~ abar_D dU + abar_A dpsi (D~ is inside alpha_D)
+      const T fN_ = bD.N * dU.N + bA.N * dP.N;
+      const T fNE = bD.NE * dU.NE + bA.NE * dP.NE;
+      const T fNW = bD.NW * dU.NW + bA.NW * dP.NW;
+      const T fNU = bD.NU * dU.NU + bA.NU * dP.NU;
+      const T fND = bD.ND * dU.ND + bA.ND * dP.ND;
+      if constexpr (kFull) {
+        const T fE = bD.E * dU.E + bA.E * dP.E;
+        const T fUp = bD.Up * dU.Up + bA.Up * dP.Up;
+        const T fEU = bD.EU * dU.EU + bA.EU * dP.EU;
+        const T fWU = bD.WU * dU.WU + bA.WU * dP.WU;
+        // links the waves above and below take with the opposite sign
+        const int par = q & 1;
+        XL[((par * 2 + 0) * NW + w) * 64 + lane] = fUp + from_left(fEU) + from_right(fWU) + NUprev;
+        XL[((par * 2 + 1) * NW + w) * 64 + lane] = NDprev;
+        T own = ((fE + fN_) + (fUp + fNE)) + ((fNW + fEU) + (fWU + fNU)) + fND;
+        T part = own - from_left(fE) - southSum;
+        if constexpr (kShell3) {
+          // <111>: mean of the 8 corners of the cube spanned by the cell and d,
+          // each cell evaluating all 8 of its links
+          T s111 = T(0);
+#pragma unroll
+          for (int sx = -1; sx <= 1; sx += 2)
+#pragma unroll
+            for (int sy = -1; sy <= 1; sy += 2)
+#pragma unroll
+              for (int sz = -1; sz <= 1; sz += 2) {
+                T cD = T(0), cA = T(0);
+#pragma unroll
+                for (int i = 0; i <= 1; ++i)
+#pragma unroll
+                  for (int j = 0; j <= 1; ++j)
+#pragma unroll
+                    for (int k = 0; k <= 1; ++k) {
+                      cD += rd(adL, j * sy, k * sz, i * sx);
+                      cA += rd(aAL, j * sy, k * sz, i * sx);
+                    }
+                s111 += cD * (rd(UL, sy, sz, sx) - rd(UL, 0, 0, 0)) +
+                        cA * (rd(psiL, sy, sz, sx) - rd(psiL, 0, 0, 0));
+              }
+          part += c.cD3 * T(0.125) * s111;
+        }
+        // finish the row below with its neighbours' links (published one
+        // iteration ago), then let row q wait
+        if (q - 1 >= y0) finalize(q - 1);
+        waitU = uS;
+        waitBase = part + sq2 * aAown[(q + 3) % 3];
+        waitDen = M::rcp(T(1) + c.k - c.omk * fS);
+      }
+      southSum = fN_ + from_left(fNE) + from_right(fNW);
+      NUprev = fNU;
+      NDprev = fND;
     }
   };
   using I0 = std::integral_constant<int, 0>;
@@ -449,6 +502,9 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
   iter(I2{}, y0);
   iter(I3{}, y0 + 1);
   for (int r = y0 + 2; r <= ye + 1; ++r) iter(I4{}, r);
+  // the last row's neighbours published their links in the last iteration
+  __syncthreads();
+  finalize(ye - 1);
 
   if (kReduce) {
     const bool any = __any(over && out_wave);
@@ -478,7 +534,24 @@ Geom3D geom3d(int nx, int ny, int nz, int seg, int ztile) {
 }
 
 size_t step3d_lds_bytes(int ztile, size_t elem) {
-  return (size_t)20 * (size_t)(ztile + 4) * (size_t)kRS * elem;
+  // four 5-row rings of (ztile + 4) z layers, and the link exchange
+  return ((size_t)20 * (size_t)(ztile + 4) * (size_t)kRS + (size_t)4 * (size_t)(ztile + 2) * 64) *
+         elem;
+}
+
+// Launch one instantiation; workgroups above 64 KB of LDS need the kernel's
+// dynamic-LDS limit raised once (gfx950 allows up to 160 KB per workgroup).
+template <typename T, bool F, bool R, bool MU, bool S3>
+hipError_t launch3(const Step3DArgs<T> &a, dim3 grid, dim3 block, size_t lds, hipStream_t st) {
+  static size_t allowed = 65536;
+  if (lds > allowed) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step3d_kernel<T, F, R, MU, S3>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    allowed = lds;
+  }
+  hipLaunchKernelGGL((step3d_kernel<T, F, R, MU, S3>), grid, block, lds, st, a);
+  return hipSuccess;
 }
 
 template <typename T>
@@ -487,8 +560,8 @@ hipError_t launch_step3d(const Step3DArgs<T> &a, const Geom3D &g, bool frozen, b
   dim3 grid(g.blocks), block(g.threads);
   size_t lds = step3d_lds_bytes(g.ztile, sizeof(T));
   const bool shell3 = a.c.cD3 != T(0) || a.c.cL3 != T(0) || a.c.cG3 != T(0);
-#define PF_L3(F, R, MU, S3) \
-  hipLaunchKernelGGL((step3d_kernel<T, F, R, MU, S3>), grid, block, lds, st, a)
+  hipError_t e = hipSuccess;
+#define PF_L3(F, R, MU, S3) e = launch3<T, F, R, MU, S3>(a, grid, block, lds, st)
 #define PF_L3S(F, R, MU) \
   do { if (shell3) PF_L3(F, R, MU, true); else PF_L3(F, R, MU, false); } while (0)
   if (frozen) {
@@ -500,6 +573,7 @@ hipError_t launch_step3d(const Step3DArgs<T> &a, const Geom3D &g, bool frozen, b
   }
 #undef PF_L3S
 #undef PF_L3
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
