@@ -31,12 +31,17 @@ PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector (published)
 # FP32 operations per cell-update of the 2D step as written in step2d.hip
 # (FMA = 2, each transcendental = 1; index math, selects and cross-lane moves
-# not counted); derivation in the design doc.
+# not counted): tanh 6, y-face flux 30, psi rate 112 (L 10, G 9, centre a_s
+# 15, x-face flux 29, remainder 6, thermal 6, bulk, rate and alpha_A 20,
+# update 2, the rest 15), U update 67.
 ALG_FLOPS_2D = 215
 # compulsory bytes per cell-update: read psi, U; write psi, U (FP32)
 ALG_BYTES_2D_F32 = 16
 # FP32 operations per cell-update of the 3D step as written in step3d.hip
-# (same counting rules; derivation in the design doc)
+# (same counting rules): psi rate 405 (phi 6, L 37, G 30, centre a_s 39, four
+# face fluxes 248, remainder 17, thermal and rate 28), U update 187 (the alpha
+# sums of the 9 links a cell owns 2 x 57, their differences 18 and products
+# 27, the exchange, sums and update 26, alpha_D 2).
 ALG_FLOPS_3D = 592
 # read psi, U, the int8 grain; write psi, U
 ALG_BYTES_3D_F32 = 17
