@@ -485,7 +485,9 @@ def main():
                 "hbm_algorithmic_GBs": round(achieved_gbs, 1),
                 "hbm_frac": round(achieved_gbs / PEAK_HBM_GBS, 4),
                 "flops_per_cell": wk["flops"], "bytes_per_cell": wk["bytes"],
-                "valu_issue_frac": None if ctr is None else round(ctr["valu_issue_utilisation"], 3),
+                "valu_lane_instr_per_cell": None if ctr is None else round(ctr["valu_lane_instr_per_cell"], 1),
+                "cycles_per_valu_instr_per_simd":
+                    None if ctr is None else round(ctr["cycles_per_valu_instr_per_simd"], 2),
                 "counters_kernel_ns": None if ctr is None else ctr["avg_duration_ns"]}
 
     cpu = None
