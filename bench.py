@@ -43,6 +43,10 @@ ALG_BYTES_2D_F32 = 16
 # sums of the 9 links a cell owns 2 x 57, their differences 18 and products
 # 27, the exchange, sums and update 26, alpha_D 2).
 ALG_FLOPS_3D = 592
+# with the <111> shell (S-bar_{4,4,1}): + 32 for its Laplacian and gradient
+# square terms, + 37 for its 4 owned divergence links (cube sums from the
+# plaquette sums, differences, products, exchange)
+ALG_FLOPS_3D_441 = 661
 # read psi, U, the int8 grain; write psi, U
 ALG_BYTES_3D_F32 = 17
 # FP32 operations per cell-update of the 2D step under the three schemes of
@@ -84,6 +88,13 @@ WORKLOADS = {
         steps=300, warmup=20, cpu_steps=3, build=lambda wl: wl.config_polycrystal_3d(),
         text="3D polycrystal, 256^3, 8 Voronoi grains with uniform random cubic orientations, "
              "S-bar_{1,2,0}, FP32 fields"),
+    "polycrystal3d_441": dict(
+        sources=["paper_2110_12448_amd/csrc/step3d.hip", "paper_2110_12448_amd/csrc/pf_device.hpp"],
+        counters="profiles/step3d_polycrystal441_256cubed_counters.json",
+        kernel="step3d_kernel<float,frozen,multigrain,shell111>", flops=ALG_FLOPS_3D_441,
+        bytes=ALG_BYTES_3D_F32, steps=200, warmup=10, cpu_steps=2,
+        build=lambda wl: wl.config_polycrystal_3d(scheme="iso441"),
+        text="3D polycrystal, 256^3, 8 Voronoi grains, S-bar_{4,4,1} (27-point, <111> shell), FP32"),
     "polycrystal3d_512": dict(
         sources=["paper_2110_12448_amd/csrc/step3d.hip", "paper_2110_12448_amd/csrc/pf_device.hpp"],
         counters="profiles/step3d_polycrystal_512cubed_counters.json",

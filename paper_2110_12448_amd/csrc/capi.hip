@@ -266,6 +266,7 @@ Coef<T> coef_of(const pf_solver *s) {
     c.k1b = (T)(s->w[0] / h2 / 16.0);
     c.k2a = (T)(s->w[1] / (4.0 * h2) * 3.0 / 16.0);
     c.k2b = (T)(s->w[1] / (4.0 * h2) / 32.0);
+    c.k3 = (T)(s->w[2] / (4.0 * h2) / 8.0);
   }
   return c;
 }

@@ -61,6 +61,7 @@ struct Coef {
   T an1, an8;       // 1 + eps4, 8 eps4 (2D a_s = 1 + eps4 - 8 eps4 u^2 v^2)
   T k1a, k1b;       // cD1/4, cD1/16: <100> link alpha weights times the shell coefficient (3D)
   T k2a, k2b;       // 3 cD2/16, cD2/32: the same for <110> links (3D)
+  T k3;             // cD3/8: <111> links, mean of the 8 cube corners (3D)
 };
 
 template <typename T>

@@ -90,13 +90,16 @@ constexpr int kRS = 66;  // LDS row stride: lane l at l + 1, pads at 0 and 65
 // P = alpha/4 + (sum of the 4 neighbours across the link axis)/16; <110>
 // links abar = 3/16 (in-plane plaquette) + 1/32 (the two plaquettes beside
 // it along the third axis).  Py1 is P_y of the cell one row up, carried.
+// <111> links (sx, +1, sz): abar = mean of the 8 corners of the cube.
 template <typename T>
 struct Abar9 {
   T E, N, Up, NE, NW, EU, WU, NU, ND, Py1;
+  T Tpp, Tmp, Tpm, Tmm;  // <111> links (+1,+1,+1), (-1,+1,+1), (+1,+1,-1), (-1,+1,-1)
 };
 template <typename T>
 struct Diff9 {
   T E, N, Up, NE, NW, EU, WU, NU, ND;
+  T Tpp, Tmp, Tpm, Tmm;
 };
 
 // FP32 workgroups run up to 10 waves (ztile <= 8); FP64 ones up to 4
@@ -390,6 +393,15 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
         const T S = c0 + cp, Sd = cm + c0;
         o.NU = c.k2a * S + c.k2b * (from_left(S) + from_right(S));
         o.ND = c.k2a * Sd + c.k2b * (from_left(Sd) + from_right(Sd));
+        if constexpr (kShell3) {
+          // the cube {x, x+1} x {q, q+1} x {z, z+1} is two stacked plaquettes
+          o.Tpp = c.k3 * (X0 + Xp);
+          o.Tpm = c.k3 * (X0 + Xm);
+          o.Tmp = from_left(o.Tpp);
+          o.Tmm = from_left(o.Tpm);
+        } else {
+          o.Tpp = o.Tpm = o.Tmp = o.Tmm = T(0);
+        }
         if constexpr (kFull) {
           const T am0 = rd(AL, -1, 0, 0), am1 = rd(AL, -1, 1, 0);
           const T Px = c.k1a * a00 + c.k1b * (am0 + a10 + a0m + a0p);
@@ -415,6 +427,14 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
         o.NW = rd(BL, 1, 0, -1) - b0;
         o.NU = rd(BL, 1, 1, 0) - b0;
         o.ND = rd(BL, 1, -1, 0) - b0;
+        if constexpr (kShell3) {
+          o.Tpp = rd(BL, 1, 1, 1) - b0;
+          o.Tmp = rd(BL, 1, 1, -1) - b0;
+          o.Tpm = rd(BL, 1, -1, 1) - b0;
+          o.Tmm = rd(BL, 1, -1, -1) - b0;
+        } else {
+          o.Tpp = o.Tmp = o.Tpm = o.Tmm = T(0);
+        }
         if constexpr (kFull) {
           o.E = rd(BL, 0, 0, 1) - b0;
           o.Up = rd(BL, 0, 1, 0) - b0;
@@ -444,6 +464,19 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
       const T fNW = bD.NW * dU.NW + bA.NW * dP.NW;
       const T fNU = bD.NU * dU.NU + bA.NU * dP.NU;
       const T fND = bD.ND * dU.ND + bA.ND * dP.ND;
+      // <111> links towards +y; the wave above takes (-1,+1,+1) of lane x+1 and
+      // (+1,+1,+1) of lane x-1 as its south-down links, the wave below the
+      // (.,+1,-1) pair alike (both one row late)
+      T f111 = T(0), up111 = T(0), dn111 = T(0);
+      if constexpr (kShell3) {
+        const T fpp = bD.Tpp * dU.Tpp + bA.Tpp * dP.Tpp;
+        const T fmp = bD.Tmp * dU.Tmp + bA.Tmp * dP.Tmp;
+        const T fpm = bD.Tpm * dU.Tpm + bA.Tpm * dP.Tpm;
+        const T fmm = bD.Tmm * dU.Tmm + bA.Tmm * dP.Tmm;
+        f111 = (fpp + fmp) + (fpm + fmm);
+        up111 = from_right(fmp) + from_left(fpp);
+        dn111 = from_right(fmm) + from_left(fpm);
+      }
       if constexpr (kFull) {
         const T fE = bD.E * dU.E + bA.E * dP.E;
         const T fUp = bD.Up * dU.Up + bA.Up * dP.Up;
@@ -453,33 +486,8 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
         const int par = q & 1;
         XL[((par * 2 + 0) * NW + w) * 64 + lane] = fUp + from_left(fEU) + from_right(fWU) + NUprev;
         XL[((par * 2 + 1) * NW + w) * 64 + lane] = NDprev;
-        T own = ((fE + fN_) + (fUp + fNE)) + ((fNW + fEU) + (fWU + fNU)) + fND;
+        T own = ((fE + fN_) + (fUp + fNE)) + ((fNW + fEU) + (fWU + fNU)) + fND + f111;
         T part = own - from_left(fE) - southSum;
-        if constexpr (kShell3) {
-          // <111>: mean of the 8 corners of the cube spanned by the cell and d,
-          // each cell evaluating all 8 of its links
-          T s111 = T(0);
-#pragma unroll
-          for (int sx = -1; sx <= 1; sx += 2)
-#pragma unroll
-            for (int sy = -1; sy <= 1; sy += 2)
-#pragma unroll
-              for (int sz = -1; sz <= 1; sz += 2) {
-                T cD = T(0), cA = T(0);
-#pragma unroll
-                for (int i = 0; i <= 1; ++i)
-#pragma unroll
-                  for (int j = 0; j <= 1; ++j)
-#pragma unroll
-                    for (int k = 0; k <= 1; ++k) {
-                      cD += rd(adL, j * sy, k * sz, i * sx);
-                      cA += rd(aAL, j * sy, k * sz, i * sx);
-                    }
-                s111 += cD * (rd(UL, sy, sz, sx) - rd(UL, 0, 0, 0)) +
-                        cA * (rd(psiL, sy, sz, sx) - rd(psiL, 0, 0, 0));
-              }
-          part += c.cD3 * T(0.125) * s111;
-        }
         // finish the row below with its neighbours' links (published one
         // iteration ago), then let row q wait
         if (q - 1 >= y0) finalize(q - 1);
@@ -488,8 +496,8 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
         waitDen = M::rcp(T(1) + c.k - c.omk * fS);
       }
       southSum = fN_ + from_left(fNE) + from_right(fNW);
-      NUprev = fNU;
-      NDprev = fND;
+      NUprev = fNU + up111;
+      NDprev = fND + dn111;
     }
   };
   using I0 = std::integral_constant<int, 0>;

@@ -73,6 +73,10 @@ EDGE3 = [
     ((16, 16, 16), (0, 0, 0), "isothermal", wl.ISO_3D_441, 1, None),
     ((33, 21, 11), (0, 1, 1), "frozen", wl.ISO_3D, 3, (16, 8)),
     ((4, 12, 5), (1, 0, 1), "isothermal", wl.ISO_3D, 1, (4, 2)),
+    # <111>-shell schemes: S-bar_{4,4,1} (periodic, ragged tiles, grains) and
+    # the weights (2/3, 0, 1/3) of the <100> + <111> combination
+    ((45, 20, 14), (1, 1, 1), "isothermal", wl.ISO_3D_441, 3, (8, 4)),
+    ((30, 18, 10), (0, 0, 0), "frozen", (2.0 / 3.0, 0.0, 1.0 / 3.0), 2, (5, 3)),
 ]
 
 
@@ -106,9 +110,11 @@ def test_moving_frame_3d():
     assert max(_cmp(phi, ophi), _cmp(U, oU)) <= TOL_F64
 
 
-def test_tiles_do_not_change_results_fp32():
+@pytest.mark.parametrize("w", [wl.ISO_3D, wl.ISO_3D_441])
+def test_tiles_do_not_change_results_fp32(w):
     """Bitwise identical fields for every launch geometry."""
     pr = _poly(40, ny=36, n_grains=4, seed_radius=10.0)
+    pr["w"] = tuple(w)
     ref = run_gpu(pr, 0, 12, tune=(16, 6))
     for tune in ((4, 1), (8, 3), (32, 8), (12, 5)):
         out = run_gpu(pr, 0, 12, tune=tune)
@@ -121,4 +127,13 @@ def test_polycrystal_full_size_fp32():
     pr = wl.config_polycrystal_3d()
     ophi, oU, _, st, p = run_oracle(pr, 2)
     phi, U, psi, tip, _ = run_gpu(pr, 0, 2)
+    assert max(_cmp(phi, ophi), _cmp(U, oU)) <= TOL_F32
+
+
+def test_polycrystal_441_size_fp32():
+    """S-bar_{4,4,1} (the 27-point <111> scheme) on a 128^3 polycrystal: every
+    cell after 3 steps against the oracle."""
+    pr = wl.config_polycrystal_3d(n=128, scheme="iso441")
+    ophi, oU, _, st, p = run_oracle(pr, 3)
+    phi, U, psi, tip, _ = run_gpu(pr, 0, 3)
     assert max(_cmp(phi, ophi), _cmp(U, oU)) <= TOL_F32
