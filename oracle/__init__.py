@@ -53,7 +53,7 @@ class _Params(C.Structure):
         ("bc", C.c_int32 * 3), ("frame", C.c_int32), ("shift_row", C.c_int32),
         ("n_grains", C.c_int32), ("rot", C.POINTER(C.c_double)),
         ("round_f32", C.c_int32), ("antitrapping", C.c_int32), ("two_point", C.c_int32),
-        ("frozen_psi", C.c_int32),
+        ("frozen_psi", C.c_int32), ("dynamic_grains", C.c_int32),
     ]
 
 
@@ -90,6 +90,7 @@ def _load():
         lib.or_divergence_two_point.argtypes = [pp, dp, dp, dp]
         lib.or_antitrapping_full.argtypes = [pp, dp, dp, dp]
         lib.or_flux_gradient_appB.argtypes = [pp, dp, C.c_long, C.c_long, C.c_int, dp, dp]
+        lib.or_grain_update.argtypes = [pp, dp, i8, i8]
         lib.or_solid_fraction.argtypes = [pp, dp]
         lib.or_solid_fraction.restype = C.c_double
         lib.or_num_threads.restype = C.c_int
@@ -123,6 +124,7 @@ class Params:
     antitrapping: int = 0
     two_point: int = 0
     frozen_psi: int = 0
+    dynamic_grains: int = 0
     _keep: list = field(default_factory=list, repr=False)
 
     @classmethod
@@ -154,6 +156,7 @@ class Params:
         cp.antitrapping = int(self.antitrapping)
         cp.two_point = int(self.two_point)
         cp.frozen_psi = int(self.frozen_psi)
+        cp.dynamic_grains = int(self.dynamic_grains)
         return cp
 
 
@@ -273,12 +276,24 @@ class State:
         return "State(step=%d, shift=%d, nonfinite=%d)" % (self.step, self.shift, self.nonfinite)
 
 
+def grain_update(p: Params, psi, grain):
+    """Grain map of level n+1 from psi and the grains of level n."""
+    lib = _load()
+    psi = _f64(p, psi)
+    g, gp = _grain(p, grain)
+    out = np.empty_like(g)
+    cp = p._c()
+    lib.or_grain_update(C.byref(cp), _d(psi), gp, out.ctypes.data_as(C.POINTER(C.c_int8)))
+    return out
+
+
 def step(p: Params, psi, U, grain=None, nsteps: int = 1, state: Optional[State] = None):
-    """Advance nsteps; returns new (psi, U) arrays and the updated State."""
+    """Advance nsteps; returns new (psi, U) arrays and the updated State
+    (State.grain holds the grain map of the new level when p.dynamic_grains)."""
     lib = _load()
     psi = _f64(p, psi).copy()
     U = _f64(p, U).copy()
-    g, gp = _grain(p, grain)
+    g, gp = _grain(p, None if grain is None else np.array(grain, dtype=np.int8, copy=True))
     st = state if state is not None else State()
     cs = _State(st.step, st.shift, 0)
     cp = p._c()
@@ -286,6 +301,7 @@ def step(p: Params, psi, U, grain=None, nsteps: int = 1, state: Optional[State] 
     if rc != 0:
         raise MemoryError("oracle step failed")
     st.step, st.shift, st.nonfinite = cs.step, cs.shift, cs.nonfinite
+    st.grain = g
     return psi, U, st
 
 

@@ -641,12 +641,43 @@ double or_solid_fraction(const or_params *p, const double *phi) {
 
 /* Moving frame: drop the bottom row, move every row down by one and keep the
  * old top row as the new top row (the far field is copied in). */
-static void shift_down(const or_params *p, double *f) {
+static void shift_down_bytes(const or_params *p, void *f, size_t elem) {
   long nz = p->dim == 3 ? p->nz : 1;
-  size_t row = (size_t)p->nx;
+  size_t row = (size_t)p->nx * elem;
   for (long l = 0; l < nz; ++l) {
-    double *plane = f + (size_t)l * row * (size_t)p->ny;
-    memmove(plane, plane + row, row * (size_t)(p->ny - 1) * sizeof(double));
+    char *plane = (char *)f + (size_t)l * row * (size_t)p->ny;
+    memmove(plane, plane + row, row * (size_t)(p->ny - 1));
+  }
+}
+
+static void shift_down(const or_params *p, double *f) { shift_down_bytes(p, f, sizeof(double)); }
+
+/* READING (dynamic grains; the paper follows single grains and prints no
+ * rule): a cell that is liquid at level n (phi < 0, i.e. psi < 0) and has a
+ * solid face neighbour (psi >= 0) takes, at level n+1, the grain of the solid
+ * face neighbour with the largest psi (largest phi), the first in the order
+ * -x, +x, -y, +y, -z, +z on ties; every other cell keeps its grain.  Beyond a
+ * no-flux wall the neighbour is the cell's image. */
+void or_grain_update(const or_params *p, const double *psi, const int8_t *g, int8_t *gn) {
+  FOR_CELLS {
+    size_t c = HERE;
+    int8_t out = g[c];
+    if (psi[c] < 0.0) {
+      int found = 0;
+      double best = 0.0;
+      for (int ax = 0; ax < p->dim; ++ax)
+        for (int sg = -1; sg <= 1; sg += 2) {
+          int e[3] = {0, 0, 0};
+          e[ax] = sg;
+          double v = F(psi, e[0], e[1], e[2]);
+          if (v >= 0.0 && (!found || v > best)) {
+            best = v;
+            out = F(g, e[0], e[1], e[2]);
+            found = 1;
+          }
+        }
+    }
+    gn[c] = out;
   }
 }
 
@@ -655,13 +686,17 @@ static void shift_down(const or_params *p, double *f) {
  * dpsi/dt = rate_psi (READING: psi first, then U, all coefficients at level n).
  * With the moving frame on, the tip of phi^n decides after step n whether the
  * new state is shifted down one row (READING: at most one row per step). */
-int or_step(const or_params *p, double *psi, double *U, const int8_t *grain,
+int or_step(const or_params *p, double *psi, double *U, int8_t *grain,
             int64_t nsteps, or_state *st) {
   size_t nc = ncells(p);
   double *rp = malloc(nc * sizeof(double));
   double *ru = malloc(nc * sizeof(double));
   double *phi = malloc(nc * sizeof(double));
-  if (!rp || !ru || !phi) { free(rp); free(ru); free(phi); return -1; }
+  int8_t *gn = (p->dynamic_grains && grain) ? malloc(nc) : NULL;
+  if (!rp || !ru || !phi || (p->dynamic_grains && grain && !gn)) {
+    free(rp); free(ru); free(phi); free(gn);
+    return -1;
+  }
   for (int64_t it = 0; it < nsteps; ++it) {
     or_tip tip = {0, -1, 0, 0, 0};
     if (p->frame) {
@@ -669,6 +704,7 @@ int or_step(const or_params *p, double *psi, double *U, const int8_t *grain,
       or_tip_find(p, phi, &tip);
     }
     or_rates(p, psi, U, grain, st->step, st->shift, rp, ru);
+    if (gn) or_grain_update(p, psi, grain, gn);  /* from level n */
     for (size_t c = 0; c < nc; ++c) {
       psi[c] += p->dt * rp[c];
       U[c] += p->dt * ru[c];
@@ -678,9 +714,11 @@ int or_step(const or_params *p, double *psi, double *U, const int8_t *grain,
       }
     }
     st->step += 1;
+    if (gn) memcpy(grain, gn, nc);
     if (p->frame && tip.found && tip.y >= (double)p->shift_row * p->h) {
       shift_down(p, psi);
       shift_down(p, U);
+      if (gn) shift_down_bytes(p, grain, 1);
       st->shift += 1;
     }
   }
@@ -688,6 +726,6 @@ int or_step(const or_params *p, double *psi, double *U, const int8_t *grain,
   for (size_t c = 0; c < nc; ++c)
     if (!isfinite(psi[c]) || !isfinite(U[c])) ++bad;
   st->nonfinite = bad;
-  free(rp); free(ru); free(phi);
+  free(rp); free(ru); free(phi); free(gn);
   return 0;
 }

@@ -51,6 +51,8 @@ typedef struct or_params {
   int32_t frozen_psi;       /* 1: psi held fixed (d psi/dt = 0), U evolves by
                                Eq. PF_b alone: solute diffusion through a
                                frozen phase field */
+  int32_t dynamic_grains;   /* 1: grain indices follow solidification
+                               (or_grain_update), shifted with the frame */
 } or_params;
 
 typedef struct or_tip {
@@ -97,8 +99,15 @@ void or_rates(const or_params *p, const double *psi, const double *U,
               const int8_t *grain, int64_t n, int64_t s, double *rate_psi,
               double *rate_U);
 
-/* Advance nsteps explicit Euler steps in place; updates *st. */
-int or_step(const or_params *p, double *psi, double *U, const int8_t *grain,
+/* Grain indices of level n+1 from psi and the grains of level n (READING):
+ * a liquid cell (psi < 0) with a solid face neighbour (psi >= 0) takes the
+ * grain of the solid face neighbour with the largest psi, the first in the
+ * order -x, +x, -y, +y, -z, +z on ties; other cells keep theirs. */
+void or_grain_update(const or_params *p, const double *psi, const int8_t *g, int8_t *gn);
+
+/* Advance nsteps explicit Euler steps in place; updates *st, and the grain
+ * map in place when p->dynamic_grains. */
+int or_step(const or_params *p, double *psi, double *U, int8_t *grain,
             int64_t nsteps, or_state *st);
 
 /* Tip of the phase field phi and the solid fraction. */

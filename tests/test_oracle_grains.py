@@ -1,0 +1,99 @@
+"""Pins the oracle's dynamic grain rule (a reading: the paper follows single
+grains): solid cells keep their grain, liquid cells without a solid face
+neighbour keep theirs, a liquid cell with solid face neighbours takes the
+grain of one with the largest psi, the map commutes with lattice symmetries,
+and grown solid always carries the grain it grew from."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_12448_amd import workloads as wl
+
+
+def _neighbours(a, dim, bc):
+    """Face-neighbour values of every cell, axis by axis, with mirror (no-flux)
+    or wrap (periodic) ghosts: list of arrays, one per face."""
+    out = []
+    for ax in range(dim):
+        axis = a.ndim - 1 - ax              # x is the last array axis
+        for sg in (-1, 1):
+            if bc == oracle.PERIODIC:
+                out.append(np.roll(a, -sg, axis=axis))
+            else:
+                pad = [(0, 0)] * a.ndim
+                pad[axis] = (1, 1)
+                e = np.pad(a, pad, mode="symmetric")
+                sl = [slice(None)] * a.ndim
+                sl[axis] = slice(1 + sg, 1 + sg + a.shape[axis])
+                out.append(e[tuple(sl)])
+    return out
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("bc", [oracle.NOFLUX, oracle.PERIODIC])
+def test_rule_properties(dim, bc):
+    rng = np.random.default_rng(dim * 10 + bc)
+    shape = (9, 11) if dim == 2 else (6, 7, 8)
+    psi = rng.normal(size=shape)
+    g = rng.integers(0, 5, size=shape).astype(np.int8)
+    p = oracle.Params(dim=dim, nx=shape[-1], ny=shape[-2], nz=shape[0] if dim == 3 else 1,
+                      bc=(bc,) * 3, dynamic_grains=1)
+    gn = oracle.grain_update(p, psi, g)
+    nps = _neighbours(psi, dim, bc)
+    ngs = _neighbours(g, dim, bc)
+    solid = psi >= 0
+    n_solid = sum((q >= 0).astype(int) for q in nps)
+    assert np.array_equal(gn[solid], g[solid])
+    keep = (~solid) & (n_solid == 0)
+    assert np.array_equal(gn[keep], g[keep])
+    changed = (~solid) & (n_solid > 0)
+    assert changed.sum() > 10
+    best = np.max(np.stack([np.where(q >= 0, q, -np.inf) for q in nps]), axis=0)
+    for idx in zip(*np.nonzero(changed)):
+        cands = {int(ng[idx]) for q, ng in zip(nps, ngs) if q[idx] >= 0 and q[idx] == best[idx]}
+        assert int(gn[idx]) in cands, idx
+
+
+@pytest.mark.parametrize("bc", [oracle.NOFLUX, oracle.PERIODIC])
+def test_rule_commutes_with_lattice_symmetries(bc):
+    """Continuous random psi has no ties, so mirroring or turning the lattice
+    by a quarter turn maps the new grain map the same way."""
+    rng = np.random.default_rng(5)
+    n = 12
+    psi = rng.normal(size=(n, n))
+    g = rng.integers(0, 4, size=(n, n)).astype(np.int8)
+    p = oracle.Params(dim=2, nx=n, ny=n, bc=(bc,) * 3, dynamic_grains=1)
+    gn = oracle.grain_update(p, psi, g)
+    assert np.array_equal(oracle.grain_update(p, psi[:, ::-1], g[:, ::-1]), gn[:, ::-1])
+    assert np.array_equal(oracle.grain_update(p, np.rot90(psi).copy(), np.rot90(g).copy()),
+                          np.rot90(gn))
+
+
+def test_grown_solid_carries_its_seed_grain():
+    """Two discs of grains 1 and 2 grow into liquid marked 0: every solid cell
+    ends with grain 1 or 2 (never 0), the grain of the seed it grew from; with
+    a static map the new solid keeps 0."""
+    n = 48
+    pr = wl.problem(2, (n, n), thermal="isothermal", seed_radius=3.0, noise=0.0, seed=3,
+                    y_front=(n // 2) * 0.8, bc=(oracle.NOFLUX,) * 3,
+                    rot=np.stack([wl.rotation_2d(a) for a in (0.0, 10.0, 35.0)]))
+    x = np.arange(n) * 0.8
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    d1 = 2.4 - np.hypot(X - 12.0, Y - 19.2)
+    d2 = 2.4 - np.hypot(X - 26.4, Y - 19.2)
+    psi0 = np.maximum(d1, d2)
+    g0 = np.zeros((n, n), dtype=np.int8)
+    g0[d1 >= -1.0] = 1
+    g0[d2 >= -1.0] = 2
+    for dyn in (1, 0):
+        p = oracle.Params.from_problem(pr, dynamic_grains=dyn)
+        psi, U, st = oracle.step(p, psi0, pr["U0"], g0, 300)
+        assert st.nonfinite == 0
+        solid = psi >= 0
+        assert solid.sum() > 2 * (psi0 >= 0).sum()
+        g = st.grain
+        if dyn:
+            assert np.all(g[solid] != 0)
+            assert np.all(g[solid & (X < 15.0)] == 1) and np.all(g[solid & (X > 23.5)] == 2)
+        else:
+            assert np.array_equal(g, g0) and np.any(g[solid] == 0)
