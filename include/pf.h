@@ -99,6 +99,13 @@ typedef struct pf_params {
   const double *grain_rot; /* n_grains x 9, row-major proper rotations, crystal -> lab */
   int32_t antitrapping; /* PF_AT_APPROX (0, default) or PF_AT_FULL */
   int32_t divergence;   /* PF_DIV_SHELLS (0, default) or PF_DIV_TWO_POINT */
+  int32_t dynamic_grains; /* 0: static grain map.  1 (n_grains > 1): each step a
+                             cell that is liquid (psi < 0) with a solid face
+                             neighbour (psi >= 0) takes the grain of the solid
+                             face neighbour with the largest psi (first of -x,
+                             +x, -y, +y, -z, +z on ties), so orientations grow
+                             with the solid; the map then shifts with the
+                             moving frame and may vary along y */
 } pf_params;
 
 typedef struct pf_init {

@@ -89,7 +89,7 @@ int max_step_blocks(const pf_params *p, int seg, int ztile) {
 }
 
 struct Layout {
-  size_t psi[2], U[2], grain, rot, frame[3], partials, counter, result, total;
+  size_t psi[2], U[2], grain, grain2, rot, frame[3], partials, counter, result, total;
 };
 
 Layout layout_of(const pf_params *p) {
@@ -100,6 +100,7 @@ Layout layout_of(const pf_params *p) {
   for (int i = 0; i < 2; ++i) { L.psi[i] = o; o += align256(n * es); }
   for (int i = 0; i < 2; ++i) { L.U[i] = o; o += align256(n * es); }
   L.grain = o; o += align256(p->n_grains > 1 ? n : 1);
+  L.grain2 = o; o += align256(p->dynamic_grains ? n : 1);  // the next level's map
   L.rot = o; o += align256((size_t)(p->n_grains > 0 ? p->n_grains : 1) * 9 * es);
   for (int i = 0; i < 3; ++i) { L.frame[i] = o; o += 256; }
   // per-block partials: enough for the finest segmentation the step accepts
@@ -154,6 +155,10 @@ int validate(const pf_params *p) {
       return fail(PF_ERR_ARG, "shift_row must lie in [1, ny-2]");
   }
   if (p->n_grains < 1 || p->n_grains > 127) return fail(PF_ERR_ARG, "n_grains must be 1..127");
+  if (p->dynamic_grains != 0 && p->dynamic_grains != 1)
+    return fail(PF_ERR_ARG, "dynamic_grains must be 0 or 1");
+  if (p->dynamic_grains && p->n_grains < 2)
+    return fail(PF_ERR_ARG, "dynamic grains need n_grains >= 2");
   if (!p->grain_rot) return fail(PF_ERR_ARG, "grain_rot is NULL");
   for (int g = 0; g < p->n_grains; ++g) {
     const double *R = p->grain_rot + 9 * g;
@@ -297,13 +302,21 @@ int upload(pf_solver *s, const pf_init *init) {
   return PF_OK;
 }
 
+// Grain map k (0, 1): the static map, or the two levels of a dynamic one
+// (the current level is the solver's buffer parity, like psi and U).
+int8_t *grain_buf(pf_solver *s, int k) {
+  return reinterpret_cast<int8_t *>(s->ws + (k == 0 || !s->p.dynamic_grains ? s->L.grain
+                                                                            : s->L.grain2));
+}
+
 // Argument block of the 2D step of solver s (pointers set per launch).
 template <typename T>
 Geom2D fill2d(pf_solver *s, Step2DArgs<T> &a, int min_seg = 1) {
   const pf_params &p = s->p;
   memset(&a, 0, sizeof(a));
   Geom2D g = geom2d(p.nx, p.ny, std::max(s->seg, min_seg));
-  a.grain = p.n_grains > 1 ? reinterpret_cast<const int8_t *>(s->ws + s->L.grain) : nullptr;
+  a.grain = p.n_grains > 1 ? grain_buf(s, s->cur) : nullptr;
+  a.grain_out = p.dynamic_grains ? grain_buf(s, 1 - s->cur) : nullptr;
   a.rot = field<T>(s, s->L.rot);
   a.r00 = (T)s->rot[0]; a.r01 = (T)s->rot[1]; a.r10 = (T)s->rot[3]; a.r11 = (T)s->rot[4];
   a.nx = p.nx; a.ny = p.ny; a.bcx = p.bc[0]; a.bcy = p.bc[1];
@@ -335,6 +348,8 @@ int step_impl(pf_solver *s, long long nsteps, bool diffusion_only = false) {
       a.U_in = field<T>(s, s->L.U[s->cur]);
       a.psi_out = field<T>(s, s->L.psi[1 - s->cur]);
       a.U_out = field<T>(s, s->L.U[1 - s->cur]);
+      if (multi) a.grain = grain_buf(s, s->cur);
+      if (p.dynamic_grains) a.grain_out = grain_buf(s, 1 - s->cur);
       a.frame_in = frec(s->fcur);
       a.frame_out = frec(s->fcur + 1);
       a.frame_clear = frec(s->fcur + 2);
@@ -348,7 +363,8 @@ int step_impl(pf_solver *s, long long nsteps, bool diffusion_only = false) {
     Step3DArgs<T> a;
     memset(&a, 0, sizeof(a));
     Geom3D g = geom3d(p.nx, p.ny, p.nz, s->seg, s->ztile);
-    a.grain = multi ? reinterpret_cast<const int8_t *>(s->ws + s->L.grain) : nullptr;
+    a.grain = multi ? grain_buf(s, s->cur) : nullptr;
+    a.grain_out = p.dynamic_grains ? grain_buf(s, 1 - s->cur) : nullptr;
     a.rot = field<T>(s, s->L.rot);
     for (int i = 0; i < 9; ++i) a.R[i] = (T)s->rot[i];
     a.nx = p.nx; a.ny = p.ny; a.nz = p.nz;
@@ -363,6 +379,8 @@ int step_impl(pf_solver *s, long long nsteps, bool diffusion_only = false) {
       a.U_in = field<T>(s, s->L.U[s->cur]);
       a.psi_out = field<T>(s, s->L.psi[1 - s->cur]);
       a.U_out = field<T>(s, s->L.U[1 - s->cur]);
+      if (multi) a.grain = grain_buf(s, s->cur);
+      if (p.dynamic_grains) a.grain_out = grain_buf(s, 1 - s->cur);
       a.frame_in = frec(s->fcur);
       a.frame_out = frec(s->fcur + 1);
       a.frame_clear = frec(s->fcur + 2);
@@ -554,6 +572,7 @@ int pf_batch_create(pf_solver *const *solvers, int32_t n, pf_batch **out) {
     if (s->p.dim != 2) return fail(PF_ERR_ARG, "batched stepping is 2D only");
     if (s->p.antitrapping != PF_AT_APPROX || s->p.divergence != PF_DIV_SHELLS)
       return fail(PF_ERR_ARG, "batched stepping runs the approximated current on shell divergences");
+    if (s->p.dynamic_grains) return fail(PF_ERR_ARG, "batched stepping takes static grain maps");
     if (s->p.precision != s0->p.precision) return fail(PF_ERR_ARG, "mixed precisions in a batch");
     if ((s->p.lT > 0.0) != (s0->p.lT > 0.0) || (s->p.frame != 0) != (s0->p.frame != 0) ||
         (s->p.n_grains > 1) != (s0->p.n_grains > 1))
@@ -649,7 +668,7 @@ int pf_create(const pf_params *p, const pf_init *init, void *workspace, size_t w
     for (size_t i = 0; i < n; ++i)
       if (init->grain[i] < 0 || init->grain[i] >= p->n_grains)
         return fail(PF_ERR_ARG, "grain index outside [0, n_grains)");
-    if (p->frame) {
+    if (p->frame && !p->dynamic_grains) {  // a static map does not shift with the frame
       const int nx = p->nx, ny = p->ny, nz = p->dim == 3 ? p->nz : 1;
       for (int l = 0; l < nz; ++l)
         for (int j = 1; j < ny; ++j)
@@ -752,7 +771,19 @@ int pf_read_fields(pf_solver *s, double *phi, double *U, double *psi, int8_t *gr
                                     : read_impl<float>(s, phi, U, psi);
   if (rc != PF_OK) return rc;
   if (grain) {
-    if (s->p.n_grains > 1) {
+    if (s->p.dynamic_grains) {
+      // the current level's map, with the frame shift it may still owe
+      FrameState fr;
+      PF_HIP(hipMemcpy(&fr, s->ws + s->L.frame[s->fcur], sizeof(fr), hipMemcpyDeviceToHost));
+      std::vector<int8_t> hg(s->n);
+      PF_HIP(hipMemcpy(hg.data(), grain_buf(s, s->cur), s->n, hipMemcpyDeviceToHost));
+      const int nx = s->p.nx, ny = s->p.ny, nz = s->p.dim == 3 ? s->p.nz : 1;
+      for (int l = 0; l < nz; ++l)
+        for (int j = 0; j < ny; ++j) {
+          int jp = (s->p.frame && fr.pending) ? std::min(j + 1, ny - 1) : j;
+          memcpy(grain + ((size_t)l * ny + j) * nx, hg.data() + ((size_t)l * ny + jp) * nx, nx);
+        }
+    } else if (s->p.n_grains > 1) {
       PF_HIP(hipMemcpy(grain, s->ws + s->L.grain, s->n, hipMemcpyDeviceToHost));
     } else {
       memset(grain, 0, s->n);

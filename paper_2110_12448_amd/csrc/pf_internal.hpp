@@ -69,6 +69,7 @@ struct Step2DArgs {
   const T *psi_in, *U_in;
   T *psi_out, *U_out;
   const int8_t *grain;   // multi-grain only
+  int8_t *grain_out;     // dynamic grains only: grain map of the next level
   const T *rot;          // multi-grain only: 4 per grain (r00, r01, r10, r11)
   T r00, r01, r10, r11;  // single grain
   int nx, ny, bcx, bcy;
@@ -99,6 +100,7 @@ struct Step3DArgs {
   const T *psi_in, *U_in;
   T *psi_out, *U_out;
   const int8_t *grain;   // multi-grain only
+  int8_t *grain_out;     // dynamic grains only: grain map of the next level
   const T *rot;          // 9 per grain, row-major crystal -> lab
   T R[9];                // single grain
   int nx, ny, nz, bcx, bcy, bcz;

@@ -148,7 +148,7 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
     T uS = 0, uC = 0, uN = 0;
     T fS = 0, fC = 0, fN = 0;
     T aAS = 0, aAC = 0;
-    int gC = 0, gN = 0;
+    int gS = 0, gC = 0, gN = 0;
     T FyS = 0;  // y face flux below row r-1
     // carries of the divergence for the row pair below (q-1, q)
     T cND = 0, c1D = 0, c2D = 0, cPD = 0;
@@ -187,6 +187,7 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
       uS = uC; uC = uN;
       fS = fC; fC = fN;
       aAS = aAC;
+      gS = gC;
       gC = gN;
       pN = lp0; uN = lu0; gN = lg0;
       lp0 = lp1; lu0 = lu1; lg0 = lg1;
@@ -212,9 +213,37 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
       if constexpr (!kDiff)
         FyN = aniso_flux<T, 1>(T(0.25) * (pNE + pCE - pNW - pCW), pN - pC, c.at_eps, rot_of(gC),
                                c);
+      // dynamic grains: the grain of row m at the next level (a liquid cell,
+      // psi < 0, with a solid face neighbour takes the grain of the solid
+      // neighbour with the largest psi, first of -x, +x, -y, +y on ties)
+      auto grain_next = [&](int m) {
+        if constexpr (kMulti) {
+          if (a.grain_out != nullptr && P >= 3 && m < ye) {
+            const int gW = from_left(gC), gE = from_right(gC);
+            int gn = gC;
+            if (pC < T(0)) {
+              T best = T(0);
+              bool found = false;
+              auto take = [&](T v, int g) {
+                if (v >= T(0) && (!found || v > best)) {
+                  best = v;
+                  gn = g;
+                  found = true;
+                }
+              };
+              take(pCW, gW);
+              take(pCE, gE);
+              take(pS, gS);
+              take(pN, gN);
+            }
+            if (out_lane) a.grain_out[(size_t)m * (size_t)nx + (size_t)x] = (int8_t)gn;
+          }
+        }
+      };
       if constexpr (P >= 2 && kDiff) {
         // psi is held: copy row m and take the frame decision on it
         const int m = r - 1;
+        grain_next(m);
         if (P >= 3 && m < ye) {
           if (out_lane) a.psi_out[(size_t)m * (size_t)nx + (size_t)x] = pC;
           if (kReduce && out_lane && m <= ny - 2 && fC >= T(0) && fN < T(0)) {
@@ -225,6 +254,7 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
       } else if constexpr (P >= 2) {
         // ---------------- psi rate at row m (window rows S, C, N = m-1, m, m+1)
         const int m = r - 1;
+        grain_next(m);
         const Rot2<T> R = rot_of(gC);
         T dE = pCE - pC, dW = pCW - pC, dN = pN - pC, dS = pS - pC;
         T s10 = dE + dW + dN + dS;
@@ -388,8 +418,8 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
     iter(I2{}, y0);
     iter(I3{}, y0 + 1);
     // steady state unrolled by 6, a multiple of every register-rotation
-    // period (3 for the row window and the loads in flight, 2 for alpha_A and
-    // the grain, 1 for the carries), so the rotation costs no register moves
+    // period (3 for the row window, the grains and the loads in flight, 2 for
+    // alpha_A, 1 for the carries), so the rotation costs no register moves
     int r = y0 + 2;
     for (; r + 5 <= ye + 1; r += 6) {
       iter(I4{}, r);

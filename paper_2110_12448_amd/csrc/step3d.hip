@@ -120,6 +120,7 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
   T *adL = UL + 5 * SLOT;    // alpha_D = D~ (1 - phi)
   T *aAL = adL + 5 * SLOT;   // alpha_A
   T *XL = aAL + 5 * SLOT;    // link exchange [row parity][to above, to below][wave][lane]
+  int8_t *gL = reinterpret_cast<int8_t *>(XL + 4 * NW * 64);  // grains, 5 row slots
 
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const int lane = threadIdx.x & 63;
@@ -198,7 +199,7 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
   T pS = 0, pC = 0, pN = 0, uS = 0, uC = 0, uN = 0, fS = 0, fC = 0, fN = 0;
   T aAown[3] = {0, 0, 0};  // alpha_A of own cell at rows m-1, m (index by m mod 3)
   T FyS = 0;               // y face flux below row r-1
-  int gC = 0, gN = 0;
+  int gS = 0, gC = 0, gN = 0;
   // shared divergence links: P_y of the next row (fields D, A), the south
   // links of the row (N, NE, NW of the row below), this wave's NU and ND of
   // the row below (sent to the neighbouring waves one row late), and the row
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
   auto iter = [&](auto phase, int r) {
     constexpr int P = decltype(phase)::value;
     // ---------------- phase A: publish row r
-    pS = pC; pC = pN; uS = uC; uC = uN; fS = fC; fC = fN; gC = gN;
+    pS = pC; pC = pN; uS = uC; uC = uN; fS = fC; fC = fN; gS = gC; gC = gN;
     pN = nxt_p; uN = nxt_u; gN = nxt_g;
     const T hN = nxt_h;
     if (r + 1 <= ye + 1) {
@@ -248,6 +249,7 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
       psiL[o] = pN;
       UL[o] = uN;
       adL[o] = c.D * (T(1) - fN);
+      if (kMulti) gL[o] = (int8_t)gN;
       if (ring) psiL[(sN * NZR + zih) * kRS + lane + 1] = hN;
     }
     __syncthreads();
@@ -358,6 +360,34 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
       }
       aAL[(s0 * NZR + zi) * kRS + lane + 1] = aA;
       aAown[(m + 3) % 3] = aA;
+      // dynamic grains: the grain of row m at the next level (a liquid cell,
+      // psi < 0, with a solid face neighbour takes the grain of the solid
+      // neighbour with the largest psi, first of -x, +x, -y, +y, -z, +z)
+      if constexpr (kMulti) {
+        if (a.grain_out != nullptr && P >= 3 && m < ye) {
+          const int gW = from_left(gC), gE = from_right(gC);
+          int gn = gC;
+          if (p0 < T(0)) {
+            T best = T(0);
+            bool found = false;
+            auto take = [&](T v, int g) {
+              if (v >= T(0) && (!found || v > best)) {
+                best = v;
+                gn = g;
+                found = true;
+              }
+            };
+            take(Pn[nb(-1, 0, 0)], gW);
+            take(Pn[nb(1, 0, 0)], gE);
+            take(Pn[nb(0, -1, 0)], gS);
+            take(Pn[nb(0, 1, 0)], gN);
+            take(Pn[nb(0, 0, -1)], (int)gL[(s0 * NZR + zi - 1) * kRS + lane + 1]);
+            take(Pn[nb(0, 0, 1)], (int)gL[(s0 * NZR + zi + 1) * kRS + lane + 1]);
+          }
+          if (out_wave && out_lane)
+            a.grain_out[pz + (size_t)m * nx - (size_t)gx + (size_t)x] = (int8_t)gn;
+        }
+      }
       if (P >= 3 && m < ye && out_wave && out_lane) {
         a.psi_out[pz + (size_t)m * nx - (size_t)gx + (size_t)x] = pC + c.dt * rate;
         if (kReduce && m <= ny - 2 && fC >= T(0) && fN < T(0)) {
@@ -542,9 +572,11 @@ Geom3D geom3d(int nx, int ny, int nz, int seg, int ztile) {
 }
 
 size_t step3d_lds_bytes(int ztile, size_t elem) {
-  // four 5-row rings of (ztile + 4) z layers, and the link exchange
+  // four 5-row rings of (ztile + 4) z layers, the link exchange, and a 5-row
+  // int8 ring of grains
   return ((size_t)20 * (size_t)(ztile + 4) * (size_t)kRS + (size_t)4 * (size_t)(ztile + 2) * 64) *
-         elem;
+             elem +
+         (((size_t)5 * (size_t)(ztile + 4) * (size_t)kRS + 15) & ~(size_t)15);
 }
 
 // Launch one instantiation; workgroups above 64 KB of LDS need the kernel's

@@ -49,6 +49,7 @@ class pf_params(C.Structure):
         ("shift_row", C.c_int32), ("n_grains", C.c_int32),
         ("grain_rot", C.POINTER(C.c_double)),
         ("antitrapping", C.c_int32), ("divergence", C.c_int32),
+        ("dynamic_grains", C.c_int32),
     ]
 
 
@@ -147,6 +148,7 @@ def make_params(prob: dict, precision: int = PF_F32, scheme: Optional[int] = Non
     p.grain_rot = rot.ctypes.data_as(C.POINTER(C.c_double))
     p.antitrapping = int(prob.get("antitrapping", PF_AT_APPROX))
     p.divergence = PF_DIV_TWO_POINT if prob.get("two_point", 0) else PF_DIV_SHELLS
+    p.dynamic_grains = int(prob.get("dynamic_grains", 0))
     return p, rot
 
 

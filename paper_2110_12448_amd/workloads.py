@@ -140,14 +140,15 @@ def problem(dim: int, shape: Sequence[int], *, h: float = 0.8, k: float = 0.15,
             frame: int = 0, shift_row: Optional[int] = None,
             seed_shape: str = "disc", seed_radius: float = 10.0,
             noise: float = 0.01, seed: int = 1, antitrapping: int = 0,
-            two_point: int = 0) -> dict:
+            two_point: int = 0, dynamic_grains: int = 0) -> dict:
     """One solve: scalar parameters plus initial psi, U and grain arrays.
 
     shape is (nx, ny) in 2D and (nx, ny, nz) in 3D.  seed_shape 'disc' puts a
     disc (sphere) of radius seed_radius*h centred at ((nx/2) h, 0[, (nz/2) h]);
     'slab' puts the solid at y <= seed_radius*h.  antitrapping 1 selects the
     full current of Eq. Anti_convention (2D), two_point 1 the two-point <10>
-    divergences of the standard scheme (2D).  thermal 'frozen' uses the
+    divergences of the standard scheme (2D); dynamic_grains 1 lets grain
+    indices follow solidification.  thermal 'frozen' uses the
     frozen-temperature functions with U from a uniform c_inf = k c_l^0 (U = -1 in
     the liquid, 0 in the solid); 'isothermal' uses F1 = 1, F2 = U with U = -omega
     everywhere.
@@ -206,7 +207,7 @@ def problem(dim: int, shape: Sequence[int], *, h: float = 0.8, k: float = 0.15,
                 h=h, dt=dt, Vp=Vp, lT=lT, y0=y0, bc=tuple(bc), frame=int(frame),
                 shift_row=int(ny // 2 if shift_row is None else shift_row), rot=rot,
                 psi0=psi0, U0=U0, grain=grain, antitrapping=int(antitrapping),
-                two_point=int(two_point))
+                two_point=int(two_point), dynamic_grains=int(dynamic_grains))
 
 
 # The three 2D schemes compared in Sec. 5 (Table 1), as problem() keywords.

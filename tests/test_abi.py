@@ -32,8 +32,9 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    # pf_params: 6 int32, 3 doubles, 9 doubles, 3+3 int32, pointer, 2 int32
-    assert C.sizeof(pfiso.pf_params) == 4 * 6 + 8 * 3 + 8 * 9 + 4 * 6 + 8 + 4 * 2
+    # pf_params: 6 int32, 3 doubles, 9 doubles, 3+3 int32, pointer, 3 int32,
+    # padded to a multiple of 8
+    assert C.sizeof(pfiso.pf_params) == 4 * 6 + 8 * 3 + 8 * 9 + 4 * 6 + 8 + 4 * 3 + 4
     assert C.sizeof(pfiso.pf_tip) == 8 + 8 + 4 + 4 + 8 + 8 * 6 + 8
 
 
@@ -83,6 +84,9 @@ def test_stable_dt_and_workspace():
     (dict(rot=np.diag([1.0, 1.0, -1.0])[None]), pfiso.PF_ERR_ARG, "improper"),
     (dict(rot=wl.random_rotations(3, 1)), pfiso.PF_ERR_ARG, "about z"),
     (dict(antitrapping=2), pfiso.PF_ERR_ARG, "antitrapping"),
+    (dict(dynamic_grains=1), pfiso.PF_ERR_ARG, "n_grains >= 2"),
+    (dict(dynamic_grains=3, rot=np.stack([wl.rotation_2d(0.0), wl.rotation_2d(20.0)])),
+     pfiso.PF_ERR_ARG, "dynamic_grains"),
 ])
 def test_create_rejects_bad_parameters(over, code, needle):
     rc, msg, _ = _create(_params(**over))
