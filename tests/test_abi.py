@@ -134,3 +134,54 @@ def test_scheme_fields_validated():
     for name, kw in wl.SCHEMES_2D.items():
         p2, keep2 = pfiso.make_params(wl.problem(2, (16, 16), **kw))
         assert lib.pf_stable_dt(C.byref(p2)) > 0, (name, lib.pf_last_error().decode())
+
+
+def _init_of(pr):
+    psi = np.ascontiguousarray(pr["psi0"], dtype=np.float64)
+    U = np.ascontiguousarray(pr["U0"], dtype=np.float64)
+    ini = pfiso.pf_init(psi.ctypes.data_as(C.POINTER(C.c_double)),
+                        U.ctypes.data_as(C.POINTER(C.c_double)), None)
+    return ini, (psi, U)
+
+
+def test_caller_workspace_checked_before_use():
+    """A caller workspace smaller than pf_workspace_bytes() or not 256-byte
+    aligned is refused with PF_ERR_OOM before any device access."""
+    lib = pfiso.load()
+    pr = _params()
+    p, keep = pfiso.make_params(pr)
+    ini, arrays = _init_of(pr)
+    need = lib.pf_workspace_bytes(C.byref(p))
+    h = C.c_void_p()
+    rc = lib.pf_create(C.byref(p), C.byref(ini), C.c_void_p(1 << 20), need - 256, None, C.byref(h))
+    assert rc == pfiso.PF_ERR_OOM and "workspace" in lib.pf_last_error().decode()
+    rc = lib.pf_create(C.byref(p), C.byref(ini), C.c_void_p((1 << 20) + 16), need, None,
+                       C.byref(h))
+    assert rc == pfiso.PF_ERR_OOM and "aligned" in lib.pf_last_error().decode()
+
+
+@pytest.mark.parametrize("dims,needle", [
+    ((2, 70000, 70000, 1), "4e9"),
+    ((3, 1700, 1700, 1700), "4e9"),
+    ((2, 1 << 20, 1 << 11, 1), "plane"),
+    ((2, 1 << 11, 1 << 20, 1), "plane"),
+])
+def test_lattice_size_limits(dims, needle):
+    """Lattices whose cell count or 32-bit plane offsets would overflow the
+    kernels' index arithmetic are refused up front (in 3D the plane limits are
+    implied by the cell limit once every side is >= 4)."""
+    lib = pfiso.load()
+    pr = _params()
+    p, keep = pfiso.make_params(pr)
+    p.dim, p.nx, p.ny, p.nz = dims
+    if p.dim == 3:
+        p.weights[0], p.weights[1], p.weights[2] = 1.0 / 3.0, 2.0 / 3.0, 0.0
+        for i in range(3):
+            p.bc[i] = 1
+        rot = np.eye(3).reshape(1, 9)
+        keep2 = np.ascontiguousarray(rot)
+        p.grain_rot = keep2.ctypes.data_as(C.POINTER(C.c_double))
+        p.n_grains = 1
+        p.lT = 0.0
+    assert lib.pf_stable_dt(C.byref(p)) < 0
+    assert needle in lib.pf_last_error().decode()

@@ -204,3 +204,36 @@ def test_segment_length_does_not_change_results(prec, kw):
     for psi, U, shift in out[1:]:
         assert np.array_equal(psi, out[0][0]) and np.array_equal(U, out[0][1])
         assert shift == out[0][2]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_zero_steps_and_initial_readback(prec):
+    """pf_step(0) is a no-op and the state reads back as uploaded (FP64 exact,
+    FP32 the float-rounded input)."""
+    pf = _pf()
+    pr = wl.config_small_2d(30.0, n=70)
+    s = pf.Solver(pr, precision=prec)
+    s.step(0)
+    phi, U, psi, _ = s.read_fields()
+    conv = (lambda a: a) if prec == 1 else (lambda a: a.astype(np.float32).astype(np.float64))
+    assert np.array_equal(psi, conv(pr["psi0"])) and np.array_equal(U, conv(pr["U0"]))
+    assert s.tip_state()["step"] == 0
+    with pytest.raises(pf.PFError) as e:
+        s.step(-1)
+    assert e.value.code == pf.PF_ERR_ARG
+    with pytest.raises(pf.PFError) as e:
+        s.tune(3, 1)
+    assert e.value.code == pf.PF_ERR_ARG
+    s.close()
+
+
+def test_tune_limits_3d():
+    pf = _pf()
+    pr = wl.problem(3, (16, 16, 16))
+    s = pf.Solver(pr, precision=pf.PF_F64)
+    for seg, zt in ((8, 9), (8, 3), (300, 2)):
+        with pytest.raises(pf.PFError) as e:
+            s.tune(seg, zt)
+        assert e.value.code == pf.PF_ERR_ARG, (seg, zt)
+    s.tune(8, 2)
+    s.close()
