@@ -38,15 +38,16 @@ ALG_FLOPS_2D = 215
 # compulsory bytes per cell-update: read psi, U; write psi, U (FP32)
 ALG_BYTES_2D_F32 = 16
 # FP32 operations per cell-update of the 3D step as written in step3d.hip
-# (same counting rules): psi rate 405 (phi 6, L 37, G 30, centre a_s 39, four
-# face fluxes 248, remainder 17, thermal and rate 28), U update 187 (the alpha
-# sums of the 9 links a cell owns 2 x 57, their differences 18 and products
-# 27, the exchange, sums and update 26, alpha_D 2).
-ALG_FLOPS_3D = 592
+# (same counting rules): psi rate 343 (phi 6, L 37, G 30, centre a_s 39, three
+# face fluxes 186 (the z face below is the wave below's z face above),
+# remainder 17, thermal and rate 28), U update 187 (the alpha sums of the 9
+# links a cell owns 2 x 57, their differences 18 and products 27, the
+# exchange, sums and update 26, alpha_D 2).
+ALG_FLOPS_3D = 530
 # with the <111> shell (S-bar_{4,4,1}): + 32 for its Laplacian and gradient
 # square terms, + 37 for its 4 owned divergence links (cube sums from the
 # plaquette sums, differences, products, exchange)
-ALG_FLOPS_3D_441 = 661
+ALG_FLOPS_3D_441 = 599
 # read psi, U, the int8 grain; write psi, U
 ALG_BYTES_3D_F32 = 17
 # FP32 operations per cell-update of the 2D step under the three schemes of

@@ -120,7 +120,8 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
   T *adL = UL + 5 * SLOT;    // alpha_D = D~ (1 - phi)
   T *aAL = adL + 5 * SLOT;   // alpha_A
   T *XL = aAL + 5 * SLOT;    // link exchange [row parity][to above, to below][wave][lane]
-  int8_t *gL = reinterpret_cast<int8_t *>(XL + 4 * NW * 64);  // grains, 5 row slots
+  T *FZ = XL + 4 * NW * 64;  // z-up face flux of each wave's row [wave][lane]
+  int8_t *gL = reinterpret_cast<int8_t *>(FZ + NW * 64);  // grains, 5 row slots
 
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const int lane = threadIdx.x & 63;
@@ -327,17 +328,25 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
           (Pn[nb(1, 0, 0)] + Pn[nb(1, 1, 0)] - Pn[nb(-1, 0, 0)] - Pn[nb(-1, 1, 0)]) * qh,
           (Pn[nb(0, 1, 0)] - p0) * ih,
           (Pn[nb(0, 0, 1)] + Pn[nb(0, 1, 1)] - Pn[nb(0, 0, -1)] - Pn[nb(0, 1, -1)]) * qh, R, c);
-      // z faces above (own grain) and below (grain of the cell below)
+      // z face above (own grain); the face below is the wave below's face
+      // above (the same points in the same order, the grain of the lower
+      // cell), read after a barrier; the lowest wave computes its own
       T FzU = aniso3<T, 2>(
           (Pn[nb(1, 0, 0)] + Pn[nb(1, 0, 1)] - Pn[nb(-1, 0, 0)] - Pn[nb(-1, 0, 1)]) * qh,
           (Pn[nb(0, 1, 0)] + Pn[nb(0, 1, 1)] - Pn[nb(0, -1, 0)] - Pn[nb(0, -1, 1)]) * qh,
           (Pn[nb(0, 0, 1)] - p0) * ih, R, c);
-      Rot3<T> Rd = R;
-      if (kMulti) Rd = rot_of(a.grain[pzd + rowoff(m)]);
-      T FzD = aniso3<T, 2>(
-          (Pn[nb(1, 0, -1)] + Pn[nb(1, 0, 0)] - Pn[nb(-1, 0, -1)] - Pn[nb(-1, 0, 0)]) * qh,
-          (Pn[nb(0, 1, -1)] + Pn[nb(0, 1, 0)] - Pn[nb(0, -1, -1)] - Pn[nb(0, -1, 0)]) * qh,
-          (p0 - Pn[nb(0, 0, -1)]) * ih, Rd, c);
+      FZ[w * 64 + lane] = FzU;
+      T FzD;
+      if (w == 0) {
+        Rot3<T> Rd = R;
+        if (kMulti) Rd = rot_of(a.grain[pzd + rowoff(m)]);
+        FzD = aniso3<T, 2>(
+            (Pn[nb(1, 0, -1)] + Pn[nb(1, 0, 0)] - Pn[nb(-1, 0, -1)] - Pn[nb(-1, 0, 0)]) * qh,
+            (Pn[nb(0, 1, -1)] + Pn[nb(0, 1, 0)] - Pn[nb(0, -1, -1)] - Pn[nb(0, -1, 0)]) * qh,
+            (p0 - Pn[nb(0, 0, -1)]) * ih, Rd, c);
+      }
+      __syncthreads();
+      if (w != 0) FzD = FZ[(w - 1) * 64 + lane];
       const T ac2 = ac * ac;
       T std6 = Pn[nb(1, 0, 0)] + Pn[nb(-1, 0, 0)] + Pn[nb(0, 1, 0)] + Pn[nb(0, -1, 0)] +
                Pn[nb(0, 0, 1)] + Pn[nb(0, 0, -1)] - T(6) * p0;
@@ -572,9 +581,9 @@ Geom3D geom3d(int nx, int ny, int nz, int seg, int ztile) {
 }
 
 size_t step3d_lds_bytes(int ztile, size_t elem) {
-  // four 5-row rings of (ztile + 4) z layers, the link exchange, and a 5-row
-  // int8 ring of grains
-  return ((size_t)20 * (size_t)(ztile + 4) * (size_t)kRS + (size_t)4 * (size_t)(ztile + 2) * 64) *
+  // four 5-row rings of (ztile + 4) z layers, the link exchange, the z-face
+  // fluxes, and a 5-row int8 ring of grains
+  return ((size_t)20 * (size_t)(ztile + 4) * (size_t)kRS + (size_t)5 * (size_t)(ztile + 2) * 64) *
              elem +
          (((size_t)5 * (size_t)(ztile + 4) * (size_t)kRS + 15) & ~(size_t)15);
 }
