@@ -33,8 +33,9 @@ PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector (published)
 # (FMA = 2, each transcendental = 1; index math, selects and cross-lane moves
 # not counted): tanh 6, y-face flux 30, psi rate 112 (L 10, G 9, centre a_s
 # 15, x-face flux 29, remainder 6, thermal 6, bulk, rate and alpha_A 20,
-# update 2, the rest 15), U update 67.
-ALG_FLOPS_2D = 215
+# update 2, the rest 15), U update 61 (links of D 22 and A 18, combined 4,
+# sums, rate and update 17).
+ALG_FLOPS_2D = 209
 # compulsory bytes per cell-update: read psi, U; write psi, U (FP32)
 ALG_BYTES_2D_F32 = 16
 # FP32 operations per cell-update of the 3D step as written in step3d.hip
@@ -53,7 +54,7 @@ ALG_BYTES_3D_F32 = 17
 # FP32 operations per cell-update of the 2D step under the three schemes of
 # Table 1 (same counting rules; the full current adds three App. B gradients,
 # the two-point faces replace the shell divergences)
-SCHEME_FLOPS_2D = {"S10": 199, "S21": 297, "Sbar21": 215}
+SCHEME_FLOPS_2D = {"S10": 199, "S21": 295, "Sbar21": 209}
 # Table 1: wall time of the whole isothermal run on a Tesla P100 (context)
 PAPER_TABLE1_S = {"S10": 1359.0, "S21": 4612.0, "Sbar21": 3883.0}
 

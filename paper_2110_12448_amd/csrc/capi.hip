@@ -243,13 +243,9 @@ Coef<T> coef_of(const pf_solver *s) {
     c.cD1 = (T)(s->w[0] / (4.0 * h2));
     c.cD2 = (T)(s->w[1] / (2.0 * h2));
     c.cD3 = (T)0;
-    // full current: the same fluxes times h / |h grad psi| at the flux point
-    c.cA1 = (T)(s->w[0] / (4.0 * h));
-    c.cA2 = (T)(s->w[1] / (2.0 * h));
-    // two-point faces carry (alpha_0 + alpha_e) dbeta: /(2h^2); the full
-    // current times h / |h grad psi|: /(2h)
+    // two-point faces carry (alpha_0 + alpha_e) dbeta: /(2h^2); links of the
+    // full current carry h / |h grad psi| and enter with a factor h
     c.cT = (T)(1.0 / (2.0 * h2));
-    c.cTA = (T)(1.0 / (2.0 * h));
     c.at_eps = (T)(1e-12 * h2);
     c.ac_eps = (T)(4e-12 * h2);
     c.an1 = (T)(1.0 + p.eps4);

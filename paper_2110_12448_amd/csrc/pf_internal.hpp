@@ -54,8 +54,7 @@ struct Coef {
   T cStd;           // 1/h^2 (standard Laplacian of the eps4 remainder)
   T inv_lT;         // 1/lT (frozen temperature)
   T h;
-  T cA1, cA2;       // full anti-trapping on shell fluxes: cD1 h, cD2 h (2D)
-  T cT, cTA;        // two-point <10> faces: 1/(2h^2), and 1/(2h) for the full current
+  T cT;             // two-point <10> faces: 1/(2h^2) (2D)
   T at_eps;         // 1e-12 h^2: the |g|^2 <= 1e-12 guard for h g (face gradients, 2D)
   T ac_eps;         // 4e-12 h^2: the same guard for 2h g (centre differences, 2D)
   T an1, an8;       // 1 + eps4, 8 eps4 (2D a_s = 1 + eps4 - 8 eps4 u^2 v^2)

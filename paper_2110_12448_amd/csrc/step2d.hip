@@ -150,9 +150,9 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
     T aAS = 0, aAC = 0;
     int gS = 0, gC = 0, gN = 0;
     T FyS = 0;  // y face flux below row r-1
-    // carries of the divergence for the row pair below (q-1, q)
-    T cND = 0, c1D = 0, c2D = 0, cPD = 0;
-    T cNA = 0, c1A = 0, c2A = 0, cPA = 0;
+    // carries of the divergence for the row pair below (q-1, q): the combined
+    // north and diagonal links, and the plaquette alphas of both fields
+    T cN = 0, c1 = 0, c2 = 0, cPD = 0, cPA = 0;
     // full current only: B1 = row r-3, B2 = row r-4, and the x+-2 columns of
     // rows r-1 (C) and r-2 (S)
     T pB1 = 0, pB1W = 0, pB1E = 0, pB1E2 = 0, pB2 = 0, pB2E = 0;
@@ -299,16 +299,21 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
       }
       FyS = FyN;
 
+      // ---------------- divergences of row q = r-2.  Both fields of Eq. PF_b
+      // are combined link by link, D~ f_D + lambda f_A with D~ folded into
+      // alpha_D = D~ (1 - phi) and lambda = 1, or h for the full current (whose
+      // links carry h / |h grad psi|): one set of sums, lane moves and carries.
+      constexpr bool kFullAT = kAT == kAtFullShells || kAT == kAtFullTwoPoint;
       if constexpr (P >= 3 && kTwoPoint) {
-        // ---------------- <10> faces of row q = r-2: east face and north face
+        // <10> faces: east face of row q and north face (q+1/2)
         const int q = r - 2;
-        T aq = T(1) - fS, aq1 = T(1) - fC;
-        T fED = (aq + from_right(aq)) * (from_right(uS) - uS);
-        T fND = (aq + aq1) * (uC - uS);
+        T aq = c.D - c.D * fS, aq1 = c.D - c.D * fC;
+        T fE = (aq + from_right(aq)) * (from_right(uS) - uS);
+        T fN = (aq + aq1) * (uC - uS);
         T dE = pSE - pS, dN = pC - pS;
         T fEA = (aAS + from_right(aAS)) * dE;
         T fNA = (aAS + aAC) * dN;
-        if constexpr (kAT == kAtFullTwoPoint) {
+        if constexpr (kFullAT) {
           // |grad psi| h at the faces: normal difference and a quarter of the
           // four-point tangential difference
           T tE = pC + pCE - pB1 - pB1E;
@@ -317,95 +322,102 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
           T gN = dN * dN + T(0.0625) * (tN * tN);
           fEA *= gE > c.at_eps ? M::rsq(gE) : T(0);
           fNA *= gN > c.at_eps ? M::rsq(gN) : T(0);
+          fE += c.h * fEA;
+          fN += c.h * fNA;
+        } else {
+          fE += fEA;
+          fN += fNA;
         }
         if constexpr (P == 4) {
-          T divD = c.cT * (fED - from_left(fED) + fND - cND);
-          T divA = (kAT == kAtFullTwoPoint ? c.cTA : c.cT) * (fEA - from_left(fEA) + fNA - cNA);
-          T rU = (c.D * divD + divA + sq2 * aAS) * M::rcp(T(1) + c.k - c.omk * fS);
+          T div = c.cT * (fE - from_left(fE) + fN - cN);
+          T rU = (div + sq2 * aAS) * M::rcp(T(1) + c.k - c.omk * fS);
           if (out_lane) a.U_out[(size_t)q * (size_t)nx + (size_t)x] = uS + c.dt * rU;
         }
-        cND = fND;
-        cNA = fNA;
+        cN = fN;
       } else if constexpr (P >= 3) {
-        // ---------------- divergences on the row pair (q, q+1) = (S, C), q = r-2
-        // field D: alpha = 1 - phi, beta = U;  field A: alpha = alpha_A, beta = psi
+        // shells on the row pair (q, q+1) = (S, C): field D alpha = D~(1 - phi),
+        // beta = U; field A alpha = alpha_A, beta = psi
         const int q = r - 2;
-        T aq = T(1) - fS, aq1 = T(1) - fC;
+        T aq = c.D - c.D * fS, aq1 = c.D - c.D * fC;
         T aE = from_right(aq), aNE = from_right(aq1);
         T PD = (aq + aE + aq1 + aNE) * T(0.25);
         T PDW = from_left(PD);
         T uE = from_right(uS), uNE = from_right(uC), uNW = from_left(uC);
-        T fED = (aq + aE + PD + cPD) * (uE - uS);
-        T fND = (aq + aq1 + PD + PDW) * (uC - uS);
-        T d1D = PD * (uNE - uS), d2D = PDW * (uNW - uS);
+        T fE = (aq + aE + PD + cPD) * (uE - uS);
+        T fN = (aq + aq1 + PD + PDW) * (uC - uS);
+        T d1 = PD * (uNE - uS), d2 = PDW * (uNW - uS);
 
-        T PA = T(0), fEA = T(0), fNA = T(0), d1A = T(0), d2A = T(0);
+        T PA = T(0);
         if constexpr (!kDiff) {
           T bE = from_right(aAS), bNE = from_right(aAC);
           PA = (aAS + bE + aAC + bNE) * T(0.25);
           T PAW = from_left(PA);
-          fEA = (aAS + bE + PA + cPA) * (pSE - pS);
-          fNA = (aAS + aAC + PA + PAW) * (pC - pS);
-          d1A = PA * (pCE - pS);
-          d2A = PAW * (pCW - pS);
-        }
-
-        if constexpr (kAT == kAtFullShells) {
-          // App. B gradients (times h) at the north face (q+1/2), the north-east
-          // corner (q+1/2, x+1/2) and, for the U row, the east face (q, x+1/2);
-          // the west, north-west and south fluxes reuse the neighbours' values
-          auto inv = [&](T gx, T gy) {
-            T g2 = gx * gx + gy * gy;
-            return g2 > c.at_eps ? M::rsq(g2) : T(0);
-          };
-          const T k1 = T(35.0 / 48.0), k2 = T(1.0 / 48.0), k3 = T(1.0 / 6.0);
-          const T m1 = T(35.0 / 96.0), m2 = T(1.0 / 32.0), m3 = T(1.0 / 24.0);
-          T invN;
-          {  // face (0, 1/2): the (1/2, 0) stencil turned a quarter
-            T a1 = pCW - pSE, b1 = pCE - pSW;
-            T a2 = pNW - pB1E, b2 = pNE - pB1W;
-            T a3 = pCW2 - pSE2, b3 = pCE2 - pSW2;
-            T gx = k1 * (a1 + b1) - k2 * (a2 + b2) - k3 * (a3 + b3);
-            T gy = m1 * (a1 - b1) - m2 * (a2 - b2) - m3 * (a3 - b3);
-            invN = inv(gx, gy);
-          }
-          T invNE;
-          {  // corner (1/2, 1/2)
-            T a1 = pCE - pS, b1 = pSE - pC;
-            T a2 = pCE2 - pSW, b2 = pSE2 - pCW;
-            T a3 = pNE - pB1, b3 = pB1E - pN;
-            T gx = T(5.0 / 8.0) * (a1 + b1) - T(1.0 / 48.0) * (a2 + b2) - T(1.0 / 16.0) * (a3 + b3);
-            T gy = T(5.0 / 8.0) * (a1 - b1) - T(1.0 / 16.0) * (a2 - b2) - T(1.0 / 48.0) * (a3 - b3);
-            invNE = inv(gx, gy);
-          }
-          fNA *= invN;
-          d1A *= invNE;
-          d2A *= from_left(invNE);
-          if constexpr (P == 4) {  // face (1/2, 0)
-            T a1 = pCE - pB1, b1 = pB1E - pC;
-            T a2 = pCE2 - pB1W, b2 = pB1E2 - pCW;
-            T a3 = pNE - pB2, b3 = pB2E - pN;
-            T gx = k1 * (a1 + b1) - k2 * (a2 + b2) - k3 * (a3 + b3);
-            T gy = m1 * (a1 - b1) - m2 * (a2 - b2) - m3 * (a3 - b3);
-            fEA *= inv(gx, gy);
+          T fEA = (aAS + bE + PA + cPA) * (pSE - pS);
+          T fNA = (aAS + aAC + PA + PAW) * (pC - pS);
+          T d1A = PA * (pCE - pS);
+          T d2A = PAW * (pCW - pS);
+          if constexpr (kAT == kAtFullShells) {
+            // App. B gradients (times h) at the north face (q+1/2), the
+            // north-east corner (q+1/2, x+1/2) and, for the U row, the east face
+            // (q, x+1/2); the west, north-west and south links reuse the
+            // neighbours' values
+            auto inv = [&](T gx, T gy) {
+              T g2 = gx * gx + gy * gy;
+              return g2 > c.at_eps ? M::rsq(g2) : T(0);
+            };
+            const T k1 = T(35.0 / 48.0), k2 = T(1.0 / 48.0), k3 = T(1.0 / 6.0);
+            const T m1 = T(35.0 / 96.0), m2 = T(1.0 / 32.0), m3 = T(1.0 / 24.0);
+            T invN;
+            {  // face (0, 1/2): the (1/2, 0) stencil turned a quarter
+              T a1 = pCW - pSE, b1 = pCE - pSW;
+              T a2 = pNW - pB1E, b2 = pNE - pB1W;
+              T a3 = pCW2 - pSE2, b3 = pCE2 - pSW2;
+              T gx = k1 * (a1 + b1) - k2 * (a2 + b2) - k3 * (a3 + b3);
+              T gy = m1 * (a1 - b1) - m2 * (a2 - b2) - m3 * (a3 - b3);
+              invN = inv(gx, gy);
+            }
+            T invNE;
+            {  // corner (1/2, 1/2)
+              T a1 = pCE - pS, b1 = pSE - pC;
+              T a2 = pCE2 - pSW, b2 = pSE2 - pCW;
+              T a3 = pNE - pB1, b3 = pB1E - pN;
+              T gx = T(5.0 / 8.0) * (a1 + b1) - T(1.0 / 48.0) * (a2 + b2) -
+                     T(1.0 / 16.0) * (a3 + b3);
+              T gy = T(5.0 / 8.0) * (a1 - b1) - T(1.0 / 16.0) * (a2 - b2) -
+                     T(1.0 / 48.0) * (a3 - b3);
+              invNE = inv(gx, gy);
+            }
+            fNA *= invN;
+            d1A *= invNE;
+            d2A *= from_left(invNE);
+            if constexpr (P == 4) {  // face (1/2, 0)
+              T a1 = pCE - pB1, b1 = pB1E - pC;
+              T a2 = pCE2 - pB1W, b2 = pB1E2 - pCW;
+              T a3 = pNE - pB2, b3 = pB2E - pN;
+              T gx = k1 * (a1 + b1) - k2 * (a2 + b2) - k3 * (a3 + b3);
+              T gy = m1 * (a1 - b1) - m2 * (a2 - b2) - m3 * (a3 - b3);
+              fEA *= inv(gx, gy);
+            }
+            fE += c.h * fEA;
+            fN += c.h * fNA;
+            d1 += c.h * d1A;
+            d2 += c.h * d2A;
+          } else {
+            fE += fEA;
+            fN += fNA;
+            d1 += d1A;
+            d2 += d2A;
           }
         }
 
         if constexpr (P == 4) {
-          constexpr bool kF = kAT == kAtFullShells;
-          T fWD = -from_left(fED), fWA = -from_left(fEA);
-          T swD = -from_left(c1D), seD = -from_right(c2D);
-          T swA = -from_left(c1A), seA = -from_right(c2A);
-          T divD = c.cD1 * (fED + fWD + fND - cND) + c.cD2 * (d1D + d2D + swD + seD);
-          T divA = (kF ? c.cA1 : c.cD1) * (fEA + fWA + fNA - cNA) +
-                   (kF ? c.cA2 : c.cD2) * (d1A + d2A + swA + seA);
+          T div = c.cD1 * (fE - from_left(fE) + fN - cN) +
+                  c.cD2 * (d1 + d2 - from_left(c1) - from_right(c2));
           // the held psi has no anti-trapping current and no source
-          T rU = (kDiff ? c.D * divD : c.D * divD + divA + sq2 * aAS) *
-                 M::rcp(T(1) + c.k - c.omk * fS);
+          T rU = (kDiff ? div : div + sq2 * aAS) * M::rcp(T(1) + c.k - c.omk * fS);
           if (out_lane) a.U_out[(size_t)q * (size_t)nx + (size_t)x] = uS + c.dt * rU;
         }
-        cND = fND; c1D = d1D; c2D = d2D; cPD = PD;
-        cNA = fNA; c1A = d1A; c2A = d2A; cPA = PA;
+        cN = fN; c1 = d1; c2 = d2; cPD = PD; cPA = PA;
       }
     };
     using I0 = std::integral_constant<int, 0>;
