@@ -21,8 +21,11 @@
 // rate of row r-1 (written out as psi^{n+1} and turned into alpha_A), and the
 // U update of row r-2, which needs alpha_A on rows r-3..r-1.  Fluxes shared
 // between neighbouring cells are computed once: x-direction ones are passed
-// across lanes, y-direction ones carried to the next row.  Optionally the same
-// pass reduces the tip, solid fraction and finiteness of state n (FP64).
+// across lanes, y-direction ones carried to the next row; the two divergences
+// of Eq. PF_b are combined link by link.  With the moving frame the same pass
+// decides from the phi = 0 crossings of state n whether state n+1 moves one
+// row (FP64 crossing heights, one flag per wave); with dynamic grains it
+// writes the next level's grain map.
 //
 // Variants (template kAT) for the scheme comparison of Sec. 5 (Table 1):
 //   kAtApproxShells    the approximated current on shell fluxes (S-bar_{2,1});

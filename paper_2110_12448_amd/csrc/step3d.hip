@@ -20,14 +20,17 @@
 // waves also load the outer psi halo rows), which march up the segment in
 // lock-step.  Each iteration publishes the newest psi, U and D~(1 - phi) row
 // in LDS rings of 5 rows, then (barrier) computes the psi rate of the row
-// below from the LDS 3x3x3 neighbourhood and publishes alpha_A, then
+// below from the LDS 3x3x3 neighbourhood (its z-down face flux is the wave
+// below's z-up one, read after a barrier) and publishes alpha_A, then
 // (barrier) evaluates the divergence links of the row below that.  Every
-// link is evaluated once: a cell owns the 9 links towards +x, +y or +z and
-// takes the other 9 with the opposite sign from the lane to its left, from
-// the row below (register carries) and, for links to the z-rows below and
-// the yz links to the row below, from an exchange buffer in which each wave
-// publishes two sums per lane and row.  A row's U is therefore finished one
-// iteration later, after the next barriers.  No-flux walls: psi, U and phi
+// link is evaluated once: a cell owns the links towards +x, +y or +z (9, and
+// 4 of the <111> shell) and takes the others with the opposite sign from the
+// lane to its left, from the row below (register carries) and, for links to
+// the z-rows below and the links to the row below in other z-rows, from an
+// exchange buffer in which each wave publishes two sums per lane and row.  A
+// row's U is therefore finished one iteration later, after the next barriers.
+// With the moving frame the pass takes the frame decision as in 2D; with
+// dynamic grains it writes the next level's grain map.  No-flux walls: psi, U and phi
 // are read through the mirror map, and every field beyond a wall is read at
 // its image (alpha_A of a mirrored cell included).
 #include <type_traits>
