@@ -60,10 +60,17 @@ PAPER_TABLE1_S = {"S10": 1359.0, "S21": 4612.0, "Sbar21": 3883.0}
 
 
 def src_digest(paths):
+    """Digest of the kernel sources' code: comments and whitespace removed, so
+    that a documentation edit does not retire counters taken on the same
+    kernel."""
+    import re
     h = hashlib.sha256()
     for p in paths:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p)) as f:
+            code = f.read()
+        code = re.sub(r"/\*.*?\*/", " ", code, flags=re.S)
+        code = re.sub(r"//[^\n]*", " ", code)
+        h.update(" ".join(code.split()).encode())
     return h.hexdigest()[:16]
 
 
