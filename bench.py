@@ -79,14 +79,14 @@ WORKLOADS = {
         sources=["paper_2110_12448_amd/csrc/step2d.hip", "paper_2110_12448_amd/csrc/pf_device.hpp"],
         counters="profiles/step2d_directional_1024x2048_counters.json",
         kernel="step2d_kernel<float,frozen,frame>", flops=ALG_FLOPS_2D, bytes=ALG_BYTES_2D_F32,
-        steps=20000, warmup=500, build=lambda wl: wl.config_directional_2d(),
+        steps=20000, warmup=500, tune_steps=50, build=lambda wl: wl.config_directional_2d(),
         text="2D directional solidification, moving frame, 1024x2048, S-bar_{2,1}, FP32 "
              "fields, FP64 tip/fraction reductions"),
     "directional2d_8192": dict(
         sources=["paper_2110_12448_amd/csrc/step2d.hip", "paper_2110_12448_amd/csrc/pf_device.hpp"],
         counters="profiles/step2d_directional_8192x8192_counters.json",
         kernel="step2d_kernel<float,frozen,frame>", flops=ALG_FLOPS_2D, bytes=ALG_BYTES_2D_F32,
-        steps=1000, warmup=50, cpu_steps=2,
+        steps=1000, warmup=50, cpu_steps=2, tune_steps=10,
         build=lambda wl: wl.config_directional_2d(nx=8192, ny=8192),
         text="2D directional solidification, moving frame, 8192x8192 (1 GiB of fields, beyond "
              "the 256 MB last-level cache), S-bar_{2,1}, FP32"),
@@ -94,21 +94,21 @@ WORKLOADS = {
         sources=["paper_2110_12448_amd/csrc/step3d.hip", "paper_2110_12448_amd/csrc/pf_device.hpp"],
         counters="profiles/step3d_polycrystal_256cubed_counters.json",
         kernel="step3d_kernel<float,frozen,multigrain>", flops=ALG_FLOPS_3D, bytes=ALG_BYTES_3D_F32,
-        steps=300, warmup=20, cpu_steps=3, build=lambda wl: wl.config_polycrystal_3d(),
+        steps=300, warmup=20, cpu_steps=3, tune_steps=10, build=lambda wl: wl.config_polycrystal_3d(),
         text="3D polycrystal, 256^3, 8 Voronoi grains with uniform random cubic orientations, "
              "S-bar_{1,2,0}, FP32 fields"),
     "polycrystal3d_441": dict(
         sources=["paper_2110_12448_amd/csrc/step3d.hip", "paper_2110_12448_amd/csrc/pf_device.hpp"],
         counters="profiles/step3d_polycrystal441_256cubed_counters.json",
         kernel="step3d_kernel<float,frozen,multigrain,shell111>", flops=ALG_FLOPS_3D_441,
-        bytes=ALG_BYTES_3D_F32, steps=200, warmup=10, cpu_steps=2,
+        bytes=ALG_BYTES_3D_F32, steps=200, warmup=10, cpu_steps=2, tune_steps=8,
         build=lambda wl: wl.config_polycrystal_3d(scheme="iso441"),
         text="3D polycrystal, 256^3, 8 Voronoi grains, S-bar_{4,4,1} (27-point, <111> shell), FP32"),
     "polycrystal3d_512": dict(
         sources=["paper_2110_12448_amd/csrc/step3d.hip", "paper_2110_12448_amd/csrc/pf_device.hpp"],
         counters="profiles/step3d_polycrystal_512cubed_counters.json",
         kernel="step3d_kernel<float,frozen,multigrain>", flops=ALG_FLOPS_3D, bytes=ALG_BYTES_3D_F32,
-        steps=40, warmup=4, cpu_steps=1, build=lambda wl: wl.config_polycrystal_3d(n=512),
+        steps=40, warmup=4, cpu_steps=1, tune_steps=4, build=lambda wl: wl.config_polycrystal_3d(n=512),
         text="3D polycrystal, 512^3 (2.1 GiB of fields), 8 Voronoi grains, S-bar_{1,2,0}, FP32"),
 }
 
@@ -138,6 +138,9 @@ def bench_batched(args):
     ss = [pfiso.Solver(p, precision=pfiso.PF_F32) for p in prs]
     b = pfiso.Batch(ss, graph_steps=10)
     b.step(warm)
+    t_default = timed(lambda: b.step(steps))
+    seg = b.autotune(20)
+    b.step(warm)
     t = timed(lambda: b.step(steps))
     batched = cells * steps / t
     b.close()
@@ -159,6 +162,8 @@ def bench_batched(args):
                                   "misorientation uniform in [0,45] deg, S-bar_{2,1}, one launch "
                                   "per step replayed from a HIP graph", "solves": len(prs),
                       "cells": cells},
+           "autotuned_rows_per_segment": seg,
+           "default_segment_value": cells * steps / t_default,
            "one_at_a_time_f32": cells * solo_steps / t32,
            "one_at_a_time_f64": cells * (solo_steps // 2) / t64}
     print(json.dumps(out))
@@ -315,34 +320,60 @@ def bench_diffusion(args):
 def bench_serve(args):
     """Continuous-batching server on a seeded Poisson trace (mean 20 requests/s,
     80% 2D sides 256..1024, 20% 3D sides 128..192, 2000..10000 steps, FP32)
-    under an HBM budget; reports p50/p99 time-to-result and throughput."""
+    under an HBM budget and a cap of 8192 active waves, over 4 streams with
+    autotuned geometries; reports p50/p99 time-to-result and throughput, and
+    the same for three baselines on the same trace."""
     from paper_2110_12448_amd import serve
-    reqs = serve.poisson_trace(n=args.requests)
+    from paper_2110_12448_amd import pfiso
     budget = int(args.hbm_budget_gib * (1 << 30))
-    srv = serve.Server(hbm_budget_bytes=budget, chunk_steps=200, graph_steps=10)
-    t0 = time.perf_counter()
-    res = srv.run(reqs, realtime=True)
-    makespan = time.perf_counter() - t0
-    summ = serve.summarize(res, makespan, srv.busy_s)
+
+    def served(precision, **kw):
+        reqs = serve.poisson_trace(n=args.requests, precision=precision)
+        srv = serve.Server(progress=10, **kw)
+        t0 = time.perf_counter()
+        res = srv.run(reqs, realtime=True)
+        makespan = time.perf_counter() - t0
+        return reqs, serve.summarize(res, makespan, srv.busy_s)
+
+    policy = dict(max_waves=8192, streams=4, autotune_steps=5)
+    reqs, summ = served(pfiso.PF_F32, hbm_budget_bytes=budget, chunk_steps=200, graph_steps=10,
+                        **policy)
+    # baselines on the same trace: every admitted solve sharing the GPU at
+    # once (no wave cap, one stream, default geometries), and one request at a
+    # time in arrival order, each solve stepped on its own to completion (no
+    # batching, no interleaving) in FP32 and in FP64
+    base = {}
+    if not args.no_serve_baselines:
+        base["all_admitted_sharing_f32"] = served(pfiso.PF_F32, hbm_budget_bytes=budget,
+                                                  chunk_steps=200, graph_steps=10)[1]
+        for name, prec in (("one_at_a_time_f32", pfiso.PF_F32), ("one_at_a_time_f64", pfiso.PF_F64)):
+            base[name] = served(prec, hbm_budget_bytes=1, chunk_steps=1 << 30, batching=False)[1]
     out = {"metric": "served phi+U cell-updates/s; p50/p99 time-to-result", "value":
            summ["cell_updates_per_s"], "unit": "cell-updates/s", "n_gpus": 1,
            "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "served mix: Poisson arrivals mean 20/s, 80%% 2D 256^2-1024^2, "
                                   "20%% 3D 128^3-192^3, 2000-10000 steps, FP32, HBM budget %.1f GiB"
-                                  % args.hbm_budget_gib, "requests": len(reqs)},
-           "serving": summ}
+                                  % args.hbm_budget_gib, "requests": len(reqs),
+                      "policy": "admit in arrival order while under the HBM budget and "
+                                "under %d active waves; 2D solves batched per kind; other "
+                                "solves over %d streams; autotuned geometries"
+                                % (policy["max_waves"], policy["streams"])},
+           "serving": summ, **base}
     print(json.dumps(out))
 
 
-def load_counters(wk):
+def load_counters(wk, geometry):
     """The committed rocprofv3 counter summary of the workload's step kernel,
-    if it was taken on the current kernel source; else None."""
+    if it was taken on the current kernel source at the launch geometry in use
+    (rows per segment, z rows per workgroup); else None."""
     path = os.path.join(ROOT, wk["counters"])
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
     if d.get("source_digest") != src_digest(wk["sources"]):
+        return None
+    if d.get("geometry") != list(geometry):
         return None
     return d
 
@@ -422,8 +453,13 @@ def main():
                                                              "diffusion2d"],
                     default="directional2d")
     ap.add_argument("--requests", type=int, default=100)
+    ap.add_argument("--no-serve-baselines", action="store_true",
+                    help="serve: skip the one-at-a-time FP32/FP64 runs of the same trace")
     ap.add_argument("--hbm-budget-gib", type=float, default=2.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--geometry", default="auto",
+                    help="launch geometry of the step kernel: 'auto' (pf_autotune before the "
+                         "warm-up), 'default' (the library's), or 'SEG,ZTILE'")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -459,9 +495,14 @@ def main():
     cells = pr["nx"] * pr["ny"] * pr["nz"]
     s = pfiso.Solver(pr, precision=pfiso.PF_F32, device="cuda:0")
     st = s.stream
-    print("bench: %s %dx%dx%d FP32, warmup %d, steps %d" %
-          (args.workload, pr["nx"], pr["ny"], pr["nz"], args.warmup, args.steps),
-          file=sys.stderr, flush=True)
+    if args.geometry == "auto":
+        s.autotune(wk["tune_steps"])
+    elif args.geometry != "default":
+        s.tune(*[int(v) for v in args.geometry.split(",")])
+    geometry = s.geometry()
+    print("bench: %s %dx%dx%d FP32, warmup %d, steps %d, geometry %s (%s)" %
+          (args.workload, pr["nx"], pr["ny"], pr["nz"], args.warmup, args.steps, geometry,
+           args.geometry), file=sys.stderr, flush=True)
     s.step(args.warmup)
     s.tip_state()
     torch.cuda.synchronize()
@@ -495,7 +536,7 @@ def main():
     step_kernel_ms = ms_per_step
     achieved_tflops = wk["flops"] * cells / (step_kernel_ms / 1e3) / 1e12
     achieved_gbs = wk["bytes"] * cells / (step_kernel_ms / 1e3) / 1e9
-    ctr = load_counters(wk)
+    ctr = load_counters(wk, geometry)
     traffic = None if ctr is None else ctr["hbm_bytes_per_launch"]
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
@@ -543,7 +584,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": wk["text"],
                    "nx": pr["nx"], "ny": pr["ny"], "nz": pr["nz"], "h": pr["h"], "dt": pr["dt"],
-                   "k": pr["k"], "eps4": pr["eps4"], "D": pr["D"]},
+                   "k": pr["k"], "eps4": pr["eps4"], "D": pr["D"],
+                   "rows_per_segment": geometry[0], "z_tile": geometry[1],
+                   "geometry_from": {"auto": "pf_autotune"}.get(args.geometry, args.geometry)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "error_vs_oracle": err,

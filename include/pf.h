@@ -196,6 +196,23 @@ int pf_frame_state(pf_solver *s, int64_t *shift, int32_t *pending);
  * depend on it (only the work split changes); used by the tile autotuner. */
 int pf_tune(pf_solver *s, int32_t rows_per_segment, int32_t z_tile);
 
+/* The launch geometry in use (the library's default for the lattice and
+ * precision until pf_tune or pf_autotune changes it); z_tile is 1 in 2D. */
+int pf_geometry(pf_solver *s, int32_t *rows_per_segment, int32_t *z_tile);
+
+/* Tile autotuner: time each candidate launch geometry (2D: rows per segment
+ * 4..64; 3D: rows per segment 8..64 times z rows per workgroup, within the
+ * LDS of one workgroup and at most 2 z rows in FP64) over steps_per_trial
+ * steps (after 2 warm-up steps) with HIP events on the solver's stream, two
+ * interleaved passes keeping each candidate's better time, and keep the
+ * fastest as if set by pf_tune; the geometry in use stays unless another is
+ * more than 3% faster (near-equal candidates do not flip with noise).  Trials run on a scratch device copy
+ * of the workspace (one extra workspace allocated and freed here), so the
+ * solve itself neither advances nor changes; results never depend on the
+ * choice.  Synchronises.  seg and ztile (either may be NULL) receive the
+ * choice (ztile 1 in 2D).  PF_ERR_OOM when the scratch copy does not fit. */
+int pf_autotune(pf_solver *s, int32_t steps_per_trial, int32_t *seg, int32_t *ztile);
+
 /* Release the solver (and its workspace if the library allocated it). */
 void pf_destroy(pf_solver *s);
 
@@ -222,6 +239,17 @@ int pf_batch_step(pf_batch *b, int64_t nsteps);
 /* Capture steps_per_graph launches (a multiple of 2; of 6 with the moving
  * frame) into a HIP graph replayed by pf_batch_step; 0 launches directly. */
 int pf_batch_use_graph(pf_batch *b, int32_t steps_per_graph);
+
+/* Batch autotuner: time the batched step for one segment length shared by
+ * every member (4..32 rows) against the one in use (initially each member's
+ * own, at least 8 rows) over steps_per_trial steps on scratch copies of all
+ * member workspaces, with the same two passes and 3% rule as pf_autotune,
+ * then rebuild the batch with the choice (kept until the batch is destroyed;
+ * it overrides the members' own pf_tune settings inside the batch only).  The
+ * members do not advance.  Synchronises.  *seg (may be NULL) receives the
+ * choice, 0 meaning each member's own segment length.  PF_ERR_OOM when the
+ * copies do not fit. */
+int pf_batch_autotune(pf_batch *b, int32_t steps_per_trial, int32_t *seg);
 
 /* Release the batch (not its solvers). */
 void pf_batch_destroy(pf_batch *b);

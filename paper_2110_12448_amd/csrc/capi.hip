@@ -307,10 +307,10 @@ int8_t *grain_buf(pf_solver *s, int k) {
 
 // Argument block of the 2D step of solver s (pointers set per launch).
 template <typename T>
-Geom2D fill2d(pf_solver *s, Step2DArgs<T> &a, int min_seg = 1) {
+Geom2D fill2d(pf_solver *s, Step2DArgs<T> &a, int min_seg = 1, int seg_fixed = 0) {
   const pf_params &p = s->p;
   memset(&a, 0, sizeof(a));
-  Geom2D g = geom2d(p.nx, p.ny, std::max(s->seg, min_seg));
+  Geom2D g = geom2d(p.nx, p.ny, seg_fixed > 0 ? seg_fixed : std::max(s->seg, min_seg));
   a.grain = p.n_grains > 1 ? grain_buf(s, s->cur) : nullptr;
   a.grain_out = p.dynamic_grains ? grain_buf(s, 1 - s->cur) : nullptr;
   a.rot = field<T>(s, s->L.rot);
@@ -447,6 +447,7 @@ struct pf_batch {
   std::vector<long long> expect;  // solver steps the device table assumes
   std::vector<int> seg;           // segment lengths the table was built with
   int graph_steps;
+  int seg_fixed;  // > 0: rows per segment of every member (pf_batch_autotune)
   hipStream_t cap;
   hipGraph_t graph;
   hipGraphExec_t gexec;
@@ -470,7 +471,7 @@ int batch_build(pf_batch *b) {
     pf_solver *s = b->s[i];
     BatchSolve2D<T> &e = tab[i];
     memset(&e, 0, sizeof(e));
-    Geom2D g = fill2d<T>(s, e.a, kMinSegBatch2D);
+    Geom2D g = fill2d<T>(s, e.a, kMinSegBatch2D, b->seg_fixed);
     for (int k = 0; k < 2; ++k) {
       e.psi[k] = field<T>(s, s->L.psi[k]);
       e.U[k] = field<T>(s, s->L.U[k]);
@@ -556,6 +557,151 @@ int batch_step(pf_batch *b, long long nsteps) {
 
 }  // namespace
 
+namespace {
+
+// Seconds of `steps` steps of `run` on `st` (after 2 warm-up steps), or a
+// negative value when a HIP call failed.
+template <typename F>
+double time_steps(hipStream_t st, int steps, F run) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.0;
+  double out = -1.0;
+  float ms = 0.f;
+  if (run(2) == PF_OK && hipEventRecord(e0, st) == hipSuccess && run(steps) == PF_OK &&
+      hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+      hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+    out = ms * 1e-3;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return out;
+}
+
+// Index of the fastest of n candidates timed by trial(i) (seconds, negative on
+// failure; -1 returned then).  Candidate 0 is the geometry in use: each
+// candidate is timed in two interleaved passes and keeps its better time,
+// and another candidate replaces candidate 0 only when it is more than 3%
+// faster, so that timing noise between near-equal geometries does not flip
+// the choice from run to run.
+template <typename F>
+int pick_fastest(int n, F trial) {
+  std::vector<double> best(n, 1e300);
+  for (int pass = 0; pass < 2; ++pass)
+    for (int i = 0; i < n; ++i) {
+      double sec = trial(i);
+      if (sec < 0.0) return -1;
+      best[i] = std::min(best[i], sec);
+    }
+  int k = 0;
+  for (int i = 1; i < n; ++i)
+    if (best[i] < best[k]) k = i;
+  return best[k] < 0.97 * best[0] ? k : 0;
+}
+
+// A copy of solver s whose workspace is a fresh device copy of s's (the
+// caller frees clone.ws).  Stepping the copy leaves s untouched.
+int clone_solver(pf_solver *s, pf_solver &clone) {
+  void *d = nullptr;
+  PF_HIP(hipStreamSynchronize(s->stream));
+  if (hipMalloc(&d, s->L.total) != hipSuccess)
+    return fail(PF_ERR_OOM, "autotune scratch allocation of " + std::to_string(s->L.total) +
+                                " bytes failed");
+  if (hipMemcpy(d, s->ws, s->L.total, hipMemcpyDeviceToDevice) != hipSuccess) {
+    (void)hipFree(d);
+    return fail(PF_ERR_DEVICE, "autotune scratch copy failed");
+  }
+  clone = *s;
+  clone.ws = reinterpret_cast<char *>(d);
+  clone.ws_bytes = s->L.total;
+  clone.own = false;
+  return PF_OK;
+}
+
+template <typename T>
+int autotune_impl(pf_solver *s, int steps) {
+  pf_solver t;
+  int rc = clone_solver(s, t);
+  if (rc != PF_OK) return rc;
+  // (rows per segment, z rows per workgroup); the geometry in use first
+  std::vector<std::pair<int, int>> cand = {{s->seg, s->ztile}};
+  auto add = [&](int seg, int zt) {
+    if (seg != s->seg || zt != s->ztile) cand.push_back({seg, zt});
+  };
+  if (s->p.dim == 2) {
+    for (int seg : {4, 6, 8, 10, 12, 16, 24, 32, 48, 64})
+      if (seg <= std::max(4, s->p.ny)) add(seg, s->ztile);
+  } else {
+    const int zmax = s->p.precision == PF_F64 ? 2 : 8;
+    for (int zt : {1, 2, 4, 5, 6, 8})
+      for (int seg : {8, 16, 32, 64})
+        if (zt <= zmax && zt <= s->p.nz && seg <= std::max(8, s->p.ny) &&
+            step3d_lds_bytes(zt, sizeof(T)) <= kMaxLds3D)
+          add(seg, zt);
+  }
+  const int k = pick_fastest((int)cand.size(), [&](int i) {
+    t.seg = cand[i].first;
+    t.ztile = cand[i].second;
+    return time_steps(s->stream, steps, [&](int n) { return step_impl<T>(&t, n); });
+  });
+  (void)hipStreamSynchronize(s->stream);
+  (void)hipFree(t.ws);
+  if (k < 0) return fail(PF_ERR_DEVICE, "autotune trial failed");
+  s->seg = cand[k].first;
+  s->ztile = cand[k].second;
+  return PF_OK;
+}
+
+template <typename T>
+int batch_autotune_impl(pf_batch *b, int steps) {
+  PF_HIP(hipStreamSynchronize(b->stream));
+  const int n = (int)b->s.size();
+  std::vector<pf_solver> clones(n);
+  int made = 0, rc = PF_OK;
+  for (; made < n && rc == PF_OK; ++made) rc = clone_solver(b->s[made], clones[made]);
+  if (rc != PF_OK) --made;
+  pf_batch tb;
+  tb.precision = b->precision;
+  tb.frozen = b->frozen;
+  tb.frame = b->frame;
+  tb.multi = b->multi;
+  tb.stream = b->stream;
+  tb.table = nullptr;
+  tb.map = nullptr;
+  tb.graph_steps = 0;
+  tb.cap = nullptr;
+  tb.graph = nullptr;
+  tb.gexec = nullptr;
+  for (int i = 0; i < made; ++i) tb.s.push_back(&clones[i]);
+  tb.expect.assign(made, -1);
+  tb.seg.assign(made, -1);
+  // candidate 0: the segment length in use (0 = each member's own)
+  std::vector<int> cand = {b->seg_fixed};
+  for (int seg : {4, 6, 8, 12, 16, 24, 32})
+    if (seg != b->seg_fixed) cand.push_back(seg);
+  int bseg = b->seg_fixed;
+  if (rc == PF_OK) {
+    const int k = pick_fastest((int)cand.size(), [&](int i) {
+      tb.seg_fixed = cand[i];
+      tb.expect.assign(made, -1);  // rebuild with this segment length
+      return time_steps(b->stream, steps, [&](int m) { return batch_step<T>(&tb, m); });
+    });
+    if (k < 0)
+      rc = fail(PF_ERR_DEVICE, "batch autotune trial failed");
+    else
+      bseg = cand[k];
+  }
+  (void)hipStreamSynchronize(b->stream);
+  if (tb.table) (void)hipFree(tb.table);
+  if (tb.map) (void)hipFree(tb.map);
+  for (int i = 0; i < made; ++i) (void)hipFree(clones[i].ws);
+  if (rc != PF_OK) return rc;
+  b->seg_fixed = bseg;
+  rc = batch_build<T>(b);
+  if (rc != PF_OK) return rc;
+  return batch_capture<T>(b);
+}
+
+}  // namespace
+
 extern "C" {
 
 int pf_batch_create(pf_solver *const *solvers, int32_t n, pf_batch **out) {
@@ -591,6 +737,7 @@ int pf_batch_create(pf_solver *const *solvers, int32_t n, pf_batch **out) {
   b->expect.assign(n, -1);
   b->seg.assign(n, -1);
   b->graph_steps = 0;
+  b->seg_fixed = 0;
   b->graph = nullptr;
   b->gexec = nullptr;
   if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
@@ -632,6 +779,27 @@ void pf_batch_destroy(pf_batch *b) {
   if (b->map) (void)hipFree(b->map);
   if (b->cap) (void)hipStreamDestroy(b->cap);
   delete b;
+}
+
+int pf_autotune(pf_solver *s, int32_t steps_per_trial, int32_t *seg, int32_t *ztile) {
+  if (!s) return fail(PF_ERR_ARG, "solver is NULL");
+  if (steps_per_trial < 1) return fail(PF_ERR_ARG, "steps_per_trial must be >= 1");
+  int rc = s->p.precision == PF_F64 ? autotune_impl<double>(s, steps_per_trial)
+                                    : autotune_impl<float>(s, steps_per_trial);
+  if (rc != PF_OK) return rc;
+  if (seg) *seg = s->seg;
+  if (ztile) *ztile = s->p.dim == 3 ? s->ztile : 1;
+  return PF_OK;
+}
+
+int pf_batch_autotune(pf_batch *b, int32_t steps_per_trial, int32_t *seg) {
+  if (!b) return fail(PF_ERR_ARG, "batch is NULL");
+  if (steps_per_trial < 1) return fail(PF_ERR_ARG, "steps_per_trial must be >= 1");
+  int rc = b->precision == PF_F64 ? batch_autotune_impl<double>(b, steps_per_trial)
+                                  : batch_autotune_impl<float>(b, steps_per_trial);
+  if (rc != PF_OK) return rc;
+  if (seg) *seg = b->seg_fixed;
+  return PF_OK;
 }
 
 int pf_version(void) { return PF_VERSION; }
@@ -853,6 +1021,13 @@ int pf_tune(pf_solver *s, int32_t rows_per_segment, int32_t z_tile) {
     return fail(PF_ERR_ARG, "z_tile too large for the LDS of one workgroup at this precision");
   s->seg = rows_per_segment;
   if (s->p.dim == 3) s->ztile = z_tile;
+  return PF_OK;
+}
+
+int pf_geometry(pf_solver *s, int32_t *rows_per_segment, int32_t *z_tile) {
+  if (!s) return fail(PF_ERR_ARG, "solver is NULL");
+  if (rows_per_segment) *rows_per_segment = s->seg;
+  if (z_tile) *z_tile = s->p.dim == 3 ? s->ztile : 1;
   return PF_OK;
 }
 

@@ -35,8 +35,8 @@ PF_DIV_SHELLS, PF_DIV_TWO_POINT = 0, 1
 
 EXPORTED = ("pf_version", "pf_last_error", "pf_stable_dt", "pf_workspace_bytes", "pf_create",
             "pf_step", "pf_step_diffusion", "pf_synchronize", "pf_read_fields", "pf_tip_state", "pf_device_fields",
-            "pf_frame_state", "pf_tune", "pf_destroy", "pf_batch_create", "pf_batch_step",
-            "pf_batch_use_graph", "pf_batch_destroy")
+            "pf_frame_state", "pf_tune", "pf_autotune", "pf_geometry", "pf_destroy", "pf_batch_create",
+            "pf_batch_step", "pf_batch_use_graph", "pf_batch_autotune", "pf_batch_destroy")
 
 
 class pf_params(C.Structure):
@@ -98,16 +98,19 @@ def load(path: str = LIB_PATH):
     lib.pf_device_fields.argtypes = [C.c_void_p, P(C.c_void_p), P(C.c_void_p)]
     lib.pf_frame_state.argtypes = [C.c_void_p, P(C.c_int64), P(C.c_int32)]
     lib.pf_tune.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+    lib.pf_autotune.argtypes = [C.c_void_p, C.c_int32, P(C.c_int32), P(C.c_int32)]
+    lib.pf_geometry.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32)]
     lib.pf_destroy.argtypes = [C.c_void_p]
     lib.pf_destroy.restype = None
     lib.pf_batch_create.argtypes = [P(C.c_void_p), C.c_int32, P(C.c_void_p)]
     lib.pf_batch_step.argtypes = [C.c_void_p, C.c_int64]
     lib.pf_batch_use_graph.argtypes = [C.c_void_p, C.c_int32]
+    lib.pf_batch_autotune.argtypes = [C.c_void_p, C.c_int32, P(C.c_int32)]
     lib.pf_batch_destroy.argtypes = [C.c_void_p]
     lib.pf_batch_destroy.restype = None
     for name in ("pf_create", "pf_step", "pf_synchronize", "pf_read_fields", "pf_tip_state",
-                 "pf_device_fields", "pf_frame_state", "pf_tune", "pf_batch_create",
-                 "pf_batch_step", "pf_batch_use_graph"):
+                 "pf_device_fields", "pf_frame_state", "pf_tune", "pf_autotune",
+                 "pf_geometry", "pf_batch_create", "pf_batch_step", "pf_batch_use_graph", "pf_batch_autotune"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -227,6 +230,19 @@ class Solver:
     def tune(self, rows_per_segment: int, z_tile: int = 1):
         _check(load().pf_tune(self.handle, int(rows_per_segment), int(z_tile)))
 
+    def geometry(self):
+        """(rows_per_segment, z_tile) of the step launches in use."""
+        seg, zt = C.c_int32(), C.c_int32()
+        _check(load().pf_geometry(self.handle, C.byref(seg), C.byref(zt)))
+        return seg.value, zt.value
+
+    def autotune(self, steps_per_trial: int = 10):
+        """Time the candidate launch geometries on a scratch copy of the state
+        and keep the fastest; returns (rows_per_segment, z_tile)."""
+        seg, zt = C.c_int32(), C.c_int32()
+        _check(load().pf_autotune(self.handle, int(steps_per_trial), C.byref(seg), C.byref(zt)))
+        return seg.value, zt.value
+
     def close(self):
         if getattr(self, "handle", None) is not None:
             load().pf_destroy(self.handle)
@@ -257,6 +273,13 @@ class Batch:
 
     def step(self, nsteps: int = 1):
         _check(load().pf_batch_step(self.handle, int(nsteps)))
+
+    def autotune(self, steps_per_trial: int = 10):
+        """Time candidate segment lengths for the whole batch on scratch copies
+        of the members and keep the fastest; returns the rows per segment."""
+        seg = C.c_int32()
+        _check(load().pf_batch_autotune(self.handle, int(steps_per_trial), C.byref(seg)))
+        return seg.value
 
     def close(self):
         if getattr(self, "handle", None) is not None:

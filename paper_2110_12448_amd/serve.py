@@ -2,21 +2,27 @@
 
 Requests (one phase-field solve each: a problem dictionary, a step count and a
 precision) arrive over time.  The server keeps every admitted solve's fields
-resident in HBM, admits queued requests in arrival order whenever its HBM
-budget allows, and advances all active solves tick by tick: the active 2D
-solves of one kind share one batched launch per step (pf_batch_*); 3D solves
-and 2D solves on the full anti-trapping current or two-point divergences are
-launched one after the other on the same stream.  A tick stops at the
-first step count an active solve needs, so every request receives exactly its
-steps; finished requests are read back and their memory released before the
-next admission.  Because batched stepping is bitwise identical to solo
-stepping, each result is the same alone and in the mix.
+resident in HBM and admits queued requests in arrival order while its HBM
+budget allows and, optionally, while the active solves occupy fewer waves than
+a cap (so that requests run close to first-come first-served instead of all
+sharing the GPU at once).  It advances all active solves tick by tick: the
+active 2D solves of one kind share one batched launch per step (pf_batch_*);
+3D solves and 2D solves on the full anti-trapping current or two-point
+divergences are launched on their own, spread over a pool of HIP streams so
+that solves too small to fill the chip overlap.  Launch geometries can come
+from the autotuners (pf_autotune per shape class, pf_batch_autotune per batch
+kind).  A tick stops at the first step count an active solve needs, so every
+request receives exactly its steps; finished requests are read back and their
+memory released before the next admission.  Because batched stepping is
+bitwise identical to solo stepping and results do not depend on the launch
+geometry, each result is the same alone and in the mix.
 
 All arithmetic runs in libpfiso.so; this module only schedules.
 """
 from __future__ import annotations
 
 import ctypes as C
+import sys
 import time
 from dataclasses import dataclass, field
 from typing import Dict, List, Optional
@@ -64,6 +70,22 @@ def _batchable(prob: dict) -> bool:
     return prob["dim"] == 2 and not prob.get("antitrapping", 0) and not prob.get("two_point", 0)
 
 
+def estimated_waves(prob: dict) -> int:
+    """Waves one step launch of this solve occupies at the library's default
+    geometry (60 output columns per wave; 2D segments of about 8 rows; 3D
+    segments of 32 rows and workgroups of 6 z rows in 8 waves): the measure of
+    how much of the chip a solve fills on its own."""
+    strips = -(-prob["nx"] // 60)
+    if prob["dim"] == 2:
+        return strips * -(-prob["ny"] // 8)
+    return strips * -(-prob["ny"] // 32) * -(-prob["nz"] // 6) * 8
+
+
+def _shape_class(prob: dict, precision: int):
+    return (prob["dim"], prob["nx"], prob["ny"], prob["nz"], precision,
+            int(prob.get("antitrapping", 0)), int(prob.get("two_point", 0)))
+
+
 def _kind(prob: dict, precision: int):
     return (precision, prob["lT"] > 0.0, int(prob["frame"]), np.asarray(prob["rot"]).reshape(-1, 9).shape[0] > 1)
 
@@ -75,12 +97,29 @@ class _Active:
     admitted: float
     done: int = 0
     nbytes: int = 0
+    waves: int = 0
 
 
 class Server:
     def __init__(self, hbm_budget_bytes: int, chunk_steps: int = 200, device: str = "cuda:0",
-                 keep_fields: bool = False, graph_steps: int = 0):
+                 keep_fields: bool = False, graph_steps: int = 0, batching: bool = True,
+                 progress: int = 0, max_waves: Optional[int] = None, streams: int = 1,
+                 autotune_steps: int = 0):
+        """max_waves: admit a request only while the active solves occupy fewer
+        waves than this (estimated_waves; None: the HBM budget alone decides).
+        streams: HIP streams the solves are spread over (batched solves share
+        the first, the others take the rest in turn), so that launches of
+        solves too small to fill the chip can run side by side.
+        autotune_steps > 0: each unbatched solve takes the launch geometry
+        pf_autotune finds for its shape class (timed once per class, on the
+        first admission), and each batch kind the segment length
+        pf_batch_autotune finds for the first batch of 4 or more solves."""
+        self.progress = int(progress)    # > 0: a line on stderr every `progress` results
+        self.max_waves = max_waves
+        self.n_streams = max(1, int(streams))
+        self.autotune_steps = int(autotune_steps)
         self.budget = int(hbm_budget_bytes)
+        self.batching = bool(batching)
         self.chunk = int(chunk_steps)
         self.device = device
         self.keep_fields = keep_fields
@@ -100,6 +139,13 @@ class Server:
         t0 = time.perf_counter()
         skew = 0.0                       # idle time skipped in simulated mode
         batches: Dict[tuple, tuple] = {}  # kind -> (member rids, pfiso.Batch)
+        dev = torch.device(self.device)
+        pool = [torch.cuda.current_stream(dev)] + [torch.cuda.Stream(dev)
+                                                   for _ in range(self.n_streams - 1)]
+        turn = 0
+        geo: Dict[tuple, tuple] = {}      # shape class -> (rows per segment, z rows)
+        batch_seg: Dict[tuple, int] = {}  # batch kind -> rows per segment (0: members' own)
+        waves = 0
 
         def now():
             return time.perf_counter() - t0 + skew
@@ -115,10 +161,25 @@ class Server:
                 need = workspace_bytes(r.problem, r.precision)
                 if used + need > self.budget and active:
                     break
+                if self.max_waves is not None and waves >= self.max_waves and active:
+                    break
                 queue.pop(0)
-                s = pfiso.Solver(r.problem, precision=r.precision, device=self.device)
-                active.append(_Active(r, s, now(), 0, need))
+                batched = self.batching and _batchable(r.problem)
+                if batched or len(pool) == 1:
+                    st = pool[0]
+                else:
+                    st = pool[1 + turn % (len(pool) - 1)]
+                    turn += 1
+                s = pfiso.Solver(r.problem, precision=r.precision, device=self.device, stream=st)
+                if self.autotune_steps and not batched:
+                    cls = _shape_class(r.problem, r.precision)
+                    if cls not in geo:
+                        geo[cls] = s.autotune(self.autotune_steps)
+                    else:
+                        s.tune(*geo[cls])
+                active.append(_Active(r, s, now(), 0, need, estimated_waves(r.problem)))
                 used += need
+                waves += active[-1].waves
             if not active:
                 if pending:
                     wait = pending[0].arrival - now()
@@ -133,20 +194,27 @@ class Server:
             tb = time.perf_counter()
             groups: Dict[tuple, List[_Active]] = {}
             for a in active:
-                if _batchable(a.req.problem):
+                if self.batching and _batchable(a.req.problem):
                     groups.setdefault(_kind(a.req.problem, a.req.precision), []).append(a)
             for kind, members in groups.items():
                 rids = tuple(m.req.rid for m in members)
                 if kind not in batches or batches[kind][0] != rids:
                     if kind in batches:
                         batches[kind][1].close()
-                    batches[kind] = (rids, pfiso.Batch([m.solver for m in members],
-                                                       graph_steps=self.graph_steps))
+                    seg = batch_seg.get(kind, 0)
+                    if seg:
+                        for m in members:
+                            if m.solver.geometry()[0] != seg:
+                                m.solver.tune(seg, 1)
+                    b = pfiso.Batch([m.solver for m in members], graph_steps=self.graph_steps)
+                    if self.autotune_steps and kind not in batch_seg and len(members) >= 4:
+                        batch_seg[kind] = b.autotune(self.autotune_steps)
+                    batches[kind] = (rids, b)
                 batches[kind][1].step(tick)
             for kind in [k for k in batches if k not in groups]:
                 batches.pop(kind)[1].close()
             for a in active:
-                if not _batchable(a.req.problem):
+                if not (self.batching and _batchable(a.req.problem)):
                     a.solver.step(tick)
                 a.done += tick
             torch.cuda.synchronize()
@@ -165,11 +233,15 @@ class Server:
                 res = Result(a.req.rid, a.req.arrival, a.admitted, now(), a.req.steps,
                              int(np.prod(a.solver.shape)), a.req.problem["dim"], fields, tip)
                 results.append(res)
+                if self.progress and len(results) % self.progress == 0:
+                    print("served %d requests, %.1f s" % (len(results), now()), file=sys.stderr,
+                          flush=True)
                 for kind in list(batches):
                     if a.req.rid in batches[kind][0]:
                         batches.pop(kind)[1].close()
                 a.solver.close()
                 used -= a.nbytes
+                waves -= a.waves
             active = still
         for _, b in batches.values():
             b.close()

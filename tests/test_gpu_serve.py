@@ -6,13 +6,21 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 
-def test_served_equals_alone():
+POLICIES = [dict(), dict(max_waves=64, streams=3, autotune_steps=2),
+            dict(streams=2, autotune_steps=2, batching=False)]
+
+
+@pytest.mark.parametrize("policy", range(len(POLICIES)))
+def test_served_equals_alone(policy):
+    """Batching, a wave cap, several streams and autotuned geometries change
+    when and where a solve runs, never its result."""
     from paper_2110_12448_amd import pfiso, serve
     reqs = serve.poisson_trace(n=10, rate=200.0, seed=9, frac_3d=0.3, steps=(20, 60),
                                sides_2d=(64, 192), sides_3d=(16, 24))
     one = max(serve.workspace_bytes(r.problem, r.precision) for r in reqs)
-    srv = serve.Server(hbm_budget_bytes=3 * one, chunk_steps=16, keep_fields=True, graph_steps=2)
-    print("serving %d requests" % len(reqs), flush=True)
+    srv = serve.Server(hbm_budget_bytes=3 * one, chunk_steps=16, keep_fields=True, graph_steps=2,
+                       **POLICIES[policy])
+    print("serving %d requests, policy %s" % (len(reqs), POLICIES[policy]), flush=True)
     res = srv.run(reqs, realtime=False)
     assert sorted(r.rid for r in res) == list(range(len(reqs)))
     by = {r.rid: r for r in res}
