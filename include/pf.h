@@ -192,7 +192,8 @@ int pf_device_fields(pf_solver *s, void **psi, void **U);
 int pf_frame_state(pf_solver *s, int64_t *shift, int32_t *pending);
 
 /* Launch geometry of the step kernels: rows per wave segment (2D and 3D,
- * 4..256) and z rows per workgroup (3D, 1..8; ignored in 2D).  Results do not
+ * 4..256) and z rows per workgroup (3D, 1..14 in FP32, 1..2 in FP64, within
+ * the LDS of one workgroup; ignored in 2D).  Results do not
  * depend on it (only the work split changes); used by the tile autotuner. */
 int pf_tune(pf_solver *s, int32_t rows_per_segment, int32_t z_tile);
 

@@ -35,6 +35,22 @@ template <> struct Math<double> {
   static __device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
 };
 
+// ------------------------------------------------------- frame decision
+// A phi = 0 crossing between rows m and m + 1 (phi_m >= 0 > phi_{m+1}) lies
+// at height y = (m + phi_m / (phi_m - phi_{m+1})) h; the frame moves when some
+// y >= shift_row h, both sides rounded in FP64 (thr = shift_row h).  The
+// fraction lies in [0, 1], so a crossing from a row at or above shift_row
+// always qualifies and one from a row below shift_row - 1 never does (FP64
+// rounding is monotone and cannot close a gap of h): callers skip those rows
+// and only the row just below shift_row evaluates the quotient.
+template <typename T>
+__device__ __forceinline__ bool crossing_reaches(T fC, T fN, int m, int shift_row, double thr,
+                                                 double hd) {
+  if (m >= shift_row) return true;
+  const double fc = (double)fC, fn = (double)fN;
+  return ((double)m + fc / (fc - fn)) * hd >= thr;
+}
+
 // ------------------------------------------------------- cross-lane moves
 // Lane i of a wave64 holds lattice column x0 + i.  from_right() returns the
 // value of lane i + 1 (column x + 1), from_left() the value of lane i - 1;

@@ -249,10 +249,9 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
         grain_next(m);
         if (P >= 3 && m < ye) {
           if (out_lane) a.psi_out[(size_t)m * (size_t)nx + (size_t)x] = pC;
-          if (kReduce && out_lane && m <= ny - 2 && fC >= T(0) && fN < T(0)) {
-            double fc = (double)fC, fn = (double)fN;
-            over |= ((double)m + fc / (fc - fn)) * a.hd >= ythr;
-          }
+          if (kReduce && out_lane && m <= ny - 2 && m + 1 >= a.shift_row && fC >= T(0) &&
+              fN < T(0))
+            over |= crossing_reaches(fC, fN, m, a.shift_row, ythr, a.hd);
         }
       } else if constexpr (P >= 2) {
         // ---------------- psi rate at row m (window rows S, C, N = m-1, m, m+1)
@@ -293,11 +292,9 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
         }
         if (P >= 3 && m < ye) {
           if (out_lane) a.psi_out[(size_t)m * (size_t)nx + (size_t)x] = pC + c.dt * rate;
-          if (kReduce && out_lane && m <= ny - 2 && fC >= T(0) && fN < T(0)) {
-            // interface cell: phi = 0 crossing height, FP64 (frame decision)
-            double fc = (double)fC, fn = (double)fN;
-            over |= ((double)m + fc / (fc - fn)) * a.hd >= ythr;
-          }
+          if (kReduce && out_lane && m <= ny - 2 && m + 1 >= a.shift_row && fC >= T(0) &&
+              fN < T(0))  // interface cell: frame decision on its crossing height
+            over |= crossing_reaches(fC, fN, m, a.shift_row, ythr, a.hd);
         }
       }
       FyS = FyN;

@@ -105,10 +105,11 @@ struct Diff9 {
   T Tpp, Tmp, Tpm, Tmm;
 };
 
-// FP32 workgroups run up to 10 waves (ztile <= 8); FP64 ones up to 4
-// (ztile <= 2), which leaves them the whole register file.
+// FP32 workgroups run up to 16 waves (ztile <= 14, at most 128 VGPRs per
+// lane); FP64 ones up to 4 (ztile <= 2), which leaves them the whole
+// register file.
 template <typename T>
-constexpr int max_threads3d() { return sizeof(T) == 8 ? 256 : 640; }
+constexpr int max_threads3d() { return sizeof(T) == 8 ? 256 : 1024; }
 
 template <typename T, bool kFrozen, bool kReduce, bool kMulti, bool kShell3>
 __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T> a) {
@@ -402,10 +403,8 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
       }
       if (P >= 3 && m < ye && out_wave && out_lane) {
         a.psi_out[pz + (size_t)m * nx - (size_t)gx + (size_t)x] = pC + c.dt * rate;
-        if (kReduce && m <= ny - 2 && fC >= T(0) && fN < T(0)) {
-          double fc = (double)fC, fn = (double)fN;
-          over |= ((double)m + fc / (fc - fn)) * a.hd >= ythr;
-        }
+        if (kReduce && m <= ny - 2 && m + 1 >= a.shift_row && fC >= T(0) && fN < T(0))
+          over |= crossing_reaches(fC, fN, m, a.shift_row, ythr, a.hd);
       }
     }
     __syncthreads();
@@ -574,7 +573,7 @@ Geom3D geom3d(int nx, int ny, int nz, int seg, int ztile) {
   Geom3D g;
   g.nstrips = (nx + 59) / 60;
   g.wout = (nx + g.nstrips - 1) / g.nstrips;
-  g.ztile = ztile < 1 ? 1 : (ztile > 8 ? 8 : ztile);
+  g.ztile = ztile < 1 ? 1 : (ztile > 14 ? 14 : ztile);
   g.nzt = (nz + g.ztile - 1) / g.ztile;
   g.seg = seg < 1 ? 1 : seg;
   g.nsegs = (ny + g.seg - 1) / g.seg;

@@ -54,7 +54,7 @@ def test_autotune_keeps_state_and_results(case):
     if dim == 2:
         assert 4 <= seg <= 64 and zt == 1
     else:
-        assert 8 <= seg <= 64 and 1 <= zt <= (2 if prec == 1 else 8)
+        assert 8 <= seg <= 64 and 1 <= zt <= (2 if prec == 1 else 14)
     s.tune(seg, zt)                      # the choice is accepted as a manual setting
     s.step(after)
     assert _same(_state(s), want)

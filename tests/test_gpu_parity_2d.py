@@ -237,3 +237,11 @@ def test_tune_limits_3d():
         assert e.value.code == pf.PF_ERR_ARG, (seg, zt)
     s.tune(8, 2)
     s.close()
+    s = pf.Solver(pr, precision=pf.PF_F32)
+    for seg, zt in ((8, 15), (8, 0)):
+        with pytest.raises(pf.PFError) as e:
+            s.tune(seg, zt)
+        assert e.value.code == pf.PF_ERR_ARG, (seg, zt)
+    s.tune(8, 14)
+    assert s.geometry() == (8, 14)
+    s.close()

@@ -77,6 +77,8 @@ EDGE3 = [
     # the weights (2/3, 0, 1/3) of the <100> + <111> combination
     ((45, 20, 14), (1, 1, 1), "isothermal", wl.ISO_3D_441, 3, (8, 4)),
     ((30, 18, 10), (0, 0, 0), "frozen", (2.0 / 3.0, 0.0, 1.0 / 3.0), 2, (5, 3)),
+    # 16-wave workgroups with a ragged last z tile (14 + 3 rows)
+    ((50, 22, 17), (1, 0, 0), "frozen", wl.ISO_3D, 2, (8, 14)),
 ]
 
 
@@ -116,7 +118,7 @@ def test_tiles_do_not_change_results_fp32(w):
     pr = _poly(40, ny=36, n_grains=4, seed_radius=10.0)
     pr["w"] = tuple(w)
     ref = run_gpu(pr, 0, 12, tune=(16, 6))
-    for tune in ((4, 1), (8, 3), (32, 8), (12, 5)):
+    for tune in ((4, 1), (8, 3), (32, 8), (12, 5), (16, 14), (8, 11), (24, 10)):
         out = run_gpu(pr, 0, 12, tune=tune)
         assert np.array_equal(out[2], ref[2]) and np.array_equal(out[1], ref[1]), tune
 
