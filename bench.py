@@ -338,16 +338,18 @@ def bench_serve(args):
     policy = dict(max_waves=8192, streams=4, autotune_steps=5)
     reqs, summ = served(pfiso.PF_F32, hbm_budget_bytes=budget, chunk_steps=200, graph_steps=10,
                         **policy)
-    # baselines on the same trace: every admitted solve sharing the GPU at
-    # once (no wave cap, one stream, default geometries), and one request at a
-    # time in arrival order, each solve stepped on its own to completion (no
-    # batching, no interleaving) in FP32 and in FP64
+    # baselines on the same trace, with the same autotuned geometries: every
+    # admitted solve sharing the GPU at once (no wave cap, one stream), and one
+    # request at a time in arrival order, each solve stepped on its own to
+    # completion (no batching, no interleaving) in FP32 and in FP64
     base = {}
     if not args.no_serve_baselines:
         base["all_admitted_sharing_f32"] = served(pfiso.PF_F32, hbm_budget_bytes=budget,
-                                                  chunk_steps=200, graph_steps=10)[1]
+                                                  chunk_steps=200, graph_steps=10,
+                                                  autotune_steps=5)[1]
         for name, prec in (("one_at_a_time_f32", pfiso.PF_F32), ("one_at_a_time_f64", pfiso.PF_F64)):
-            base[name] = served(prec, hbm_budget_bytes=1, chunk_steps=1 << 30, batching=False)[1]
+            base[name] = served(prec, hbm_budget_bytes=1, chunk_steps=1 << 30, batching=False,
+                                autotune_steps=5)[1]
     out = {"metric": "served phi+U cell-updates/s; p50/p99 time-to-result", "value":
            summ["cell_updates_per_s"], "unit": "cell-updates/s", "n_gpus": 1,
            "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
@@ -424,22 +426,28 @@ def cpu_baseline(pr, target_s=12.0, max_steps=40, label="1024x2048 directional")
     dt = time.perf_counter() - t0
     cells = pr["nx"] * pr["ny"] * pr["nz"]
     threads = oracle.num_threads()
-    # single thread: at least one step, at most a quarter of the budget
-    oracle.set_num_threads(1)
-    t1 = time.perf_counter()
-    s1 = 0
-    q, V, st1 = pr["psi0"], pr["U0"], oracle.State()
-    while s1 < 1 or (s1 < max_steps and (time.perf_counter() - t1) < target_s / 4):
-        q, V, st1 = oracle.step(p, q, V, g, 1, st1)
-        s1 += 1
-    dt1 = time.perf_counter() - t1
-    oracle.set_num_threads(threads)
+    print("cpu baseline: %d oracle steps on %d threads in %.1f s" % (steps, threads, dt),
+          file=sys.stderr, flush=True)
+    # single thread: at least one step, at most a quarter of the budget; skipped
+    # when one step would take over a minute on one thread
+    single, single_sample = None, "skipped: one step would exceed 60 s on one thread"
+    if dt / steps * threads <= 60.0:
+        oracle.set_num_threads(1)
+        t1 = time.perf_counter()
+        s1 = 0
+        q, V, st1 = pr["psi0"], pr["U0"], oracle.State()
+        while s1 < 1 or (s1 < max_steps and (time.perf_counter() - t1) < target_s / 4):
+            q, V, st1 = oracle.step(p, q, V, g, 1, st1)
+            s1 += 1
+        dt1 = time.perf_counter() - t1
+        oracle.set_num_threads(threads)
+        single, single_sample = cells * s1 / dt1, "%d steps (%.1f s)" % (s1, dt1)
     return {"value": cells * steps / dt, "unit": "cell-updates/s", "cores": threads,
             "kind": "oracle",
             "sample": "FP64 oracle, first %d steps of the same %s solve "
                       "(%.1f s)" % (steps, label, dt),
-            "single_thread_value": cells * s1 / dt1,
-            "single_thread_sample": "%d steps (%.1f s)" % (s1, dt1),
+            "single_thread_value": single,
+            "single_thread_sample": single_sample,
             "host": _host_cpu()}, steps, psi, U, st
 
 

@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <new>
 #include <string>
+#include <tuple>
+#include <utility>
 #include <vector>
 
 #include "pf_device.hpp"
@@ -44,14 +46,28 @@ int default_seg2d(int nx, int ny) {
   long long seg = strips * ny / 4608;
   return (int)(seg < 8 ? 8 : (seg > 32 ? 32 : seg));
 }
-constexpr int kDefaultSeg3D = 32;
-// z rows per 3D workgroup: 14 in FP32 (16 waves, the most one workgroup
-// holds: one workgroup per CU at the kernel's ~110 VGPRs, with ring waves
-// costing 16/14 instead of 8/6 for two 6-row workgroups; 41.0 G
-// cell-updates/s on 256^3 against 36.7 with 6 rows and 30.7 with 8, tile
-// sweep), 2 in FP64 (4 waves, the thread limit of its launch bounds)
-constexpr int kDefaultZTile3D_F32 = 14;
-constexpr int kDefaultZTile3D_F64 = 2;
+// Default 3D geometry.  z rows per workgroup: in FP32, 14 (16 waves, the most
+// one workgroup holds: one workgroup per CU at the kernel's ~110 VGPRs, ring
+// waves costing 16/14 instead of 8/6) when that still gives at least 400
+// workgroups with 32-row segments, else 6 (two 8-wave workgroups per CU);
+// 2 in FP64 (4 waves, the thread limit of its launch bounds).  Rows per
+// segment: the longest of 32, 16, 8 that keeps 400 workgroups, else 8.  From
+// a sweep of cubes 96^3..512^3: 42.2 G cell-updates/s on 256^3 with (32, 14)
+// against 39.5 with (32, 6); 35.0 on 192^3 with (32, 6) against 27.1 with
+// (32, 14).  pf_autotune refines it per lattice.
+std::pair<int, int> default_geom3d(const pf_params *p) {
+  auto blocks = [&](int seg, int zt) { return geom3d(p->nx, p->ny, p->nz, seg, zt).blocks; };
+  int zt = 2;
+  if (p->precision != PF_F64) zt = blocks(32, 14) >= 400 ? 14 : 6;
+  zt = std::min(zt, std::max(1, p->nz));  // no idle z waves on thin lattices
+  int seg = 8;
+  for (int s : {32, 16})
+    if (blocks(s, zt) >= 400) {
+      seg = s;
+      break;
+    }
+  return {seg, zt};
+}
 constexpr size_t kMaxLds3D = 163840;  // LDS one gfx950 workgroup may allocate
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -864,9 +880,12 @@ int pf_create(const pf_params *p, const pf_init *init, void *workspace, size_t w
   s->cur = 0;
   s->fcur = 0;
   s->step = 0;
-  s->seg = p->dim == 2 ? default_seg2d(p->nx, p->ny) : kDefaultSeg3D;
-  s->ztile = std::min(p->precision == PF_F64 ? kDefaultZTile3D_F64 : kDefaultZTile3D_F32,
-                      std::max(1, p->nz));  // no idle z waves on thin lattices
+  if (p->dim == 2) {
+    s->seg = default_seg2d(p->nx, p->ny);
+    s->ztile = 1;
+  } else {
+    std::tie(s->seg, s->ztile) = default_geom3d(p);
+  }
   s->have_prev = false;
   if (workspace) {
     if (workspace_bytes < L.total || (reinterpret_cast<uintptr_t>(workspace) & 255u)) {

@@ -73,12 +73,15 @@ def _batchable(prob: dict) -> bool:
 def estimated_waves(prob: dict) -> int:
     """Waves one step launch of this solve occupies at the library's default
     geometry (60 output columns per wave; 2D segments of about 8 rows; 3D
-    segments of 32 rows and workgroups of 14 z rows in 16 waves): the measure of
-    how much of the chip a solve fills on its own."""
+    segments of 32 rows and workgroups of 14 z rows in 16 waves, or of 6 z
+    rows in 8 waves when that leaves fewer than 400 workgroups): the measure
+    of how much of the chip a solve fills on its own."""
     strips = -(-prob["nx"] // 60)
     if prob["dim"] == 2:
         return strips * -(-prob["ny"] // 8)
-    return strips * -(-prob["ny"] // 32) * -(-prob["nz"] // 14) * 16
+    col = strips * -(-prob["ny"] // 32)
+    zt = 14 if col * -(-prob["nz"] // 14) >= 400 else 6
+    return col * -(-prob["nz"] // zt) * (zt + 2)
 
 
 def _shape_class(prob: dict, precision: int):
