@@ -411,6 +411,45 @@ def _host_cpu():
     return {"nproc": os.cpu_count(), "model": model}
 
 
+def growth_observables(pr, steps=20000, every=500):
+    """Tip velocity and growth angle of the same directional solve under the
+    isotropic S-bar_{2,1} and the standard (1, 0) shell weights: the tip
+    (x, y_lab) every `every` steps; over the second half of the run, V_tip is
+    the least-squares slope of y_lab in time and the growth angle that of the
+    tip path x(y_lab) from the pulling axis y, positive towards -x, the side to which the
+    crystal's <01> axis leans for a misorientation alpha0 > 0 (so a tip
+    following the crystal axis shows alpha0, one following the gradient 0)."""
+    import numpy as np
+    from paper_2110_12448_amd import pfiso
+    from paper_2110_12448_amd import workloads as wl
+    R = np.asarray(pr["rot"])[0]
+    out = {"alpha0_deg": float(np.degrees(np.arctan2(R[1, 0], R[0, 0]))), "steps": steps}
+    for name, w in (("Sbar21", wl.ISO_2D), ("std_weights_1_0", wl.STD_2D)):
+        q = dict(pr)
+        q["w"] = tuple(w)
+        s = pfiso.Solver(q, precision=pfiso.PF_F32)
+        ts, xs, ys = [], [], []
+        for k in range(0, steps + 1, every):
+            if k:
+                s.step(every)
+            t = s.tip_state()
+            if t["found"]:
+                ts.append(t["t"]), xs.append(t["x"]), ys.append(t["y_lab"])
+        s.close()
+        ts, xs, ys = np.array(ts), np.array(xs), np.array(ys)
+        width = pr["nx"] * pr["h"]
+        xs = np.unwrap(xs * (2 * np.pi / width)) * (width / (2 * np.pi))  # periodic x
+        h = len(ts) // 2
+        if len(ts) - h < 2:
+            out[name] = None
+            continue
+        v = float(np.polyfit(ts[h:], ys[h:], 1)[0])
+        ang = float(np.degrees(np.arctan(-np.polyfit(ys[h:], xs[h:], 1)[0])))
+        out[name] = {"v_tip": v, "growth_angle_deg": ang, "tip_y_lab": float(ys[-1]),
+                     "tip_x": float(xs[-1]) % width}
+    return out
+
+
 def cpu_baseline(pr, target_s=12.0, max_steps=40, label="1024x2048 directional"):
     """The FP64 oracle on the host: steps of the same solve until target_s or
     max_steps, on all OpenMP threads; then a shorter single-thread sample."""
@@ -464,7 +503,9 @@ def main():
     ap.add_argument("--no-serve-baselines", action="store_true",
                     help="serve: skip the one-at-a-time FP32/FP64 runs of the same trace")
     ap.add_argument("--hbm-budget-gib", type=float, default=2.0)
-    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the untimed extras: CPU oracle baseline, error against the "
+                         "oracle and (directional2d) the growth observables")
     ap.add_argument("--geometry", default="auto",
                     help="launch geometry of the step kernel: 'auto' (pf_autotune before the "
                          "warm-up), 'default' (the library's), or 'SEG,ZTILE'")
@@ -561,6 +602,11 @@ def main():
 
     cpu = None
     err = None
+    obs = None
+    if not args.no_cpu and args.workload == "directional2d":
+        print("observables: S-bar_{2,1} and (1, 0) weights, %d steps each" % wk["steps"],
+              file=sys.stderr, flush=True)
+        obs = growth_observables(pr, steps=wk["steps"])
     if not args.no_cpu:
         if "cpu_steps" not in wk:
             cpu, nst, opsi, oU, ost = cpu_baseline(pr)
@@ -598,6 +644,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "error_vs_oracle": err,
+        "growth": obs,
         "tip": {"y_lab": tip["y_lab"], "x": tip["x"], "frame_shift": tip["frame_shift"],
                 "velocity": tip["velocity"], "solid_fraction": tip["solid_fraction"]},
     }
