@@ -87,6 +87,7 @@ __host__ __device__ constexpr int nb(int dx, int dy, int dz) {
 }
 
 constexpr int kRS = 66;  // LDS row stride: lane l at l + 1, pads at 0 and 65
+enum LdsField { kPsi = 0, kU = 1, kAD = 2, kAA = 3 };  // alpha_D = D~ (1 - phi), alpha_A
 
 // alpha averages of the links a cell owns, times their shell coefficient
 // (Eqs. divergence_100, divergence_110): <100> links abar = P(0) + P(d) with
@@ -119,11 +120,10 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
   T *sm = reinterpret_cast<T *>(smem_raw);
   const int Z = a.ztile, NZR = Z + 4, NW = Z + 2;
   const int SLOT = NZR * kRS;
-  T *psiL = sm;              // 5 row slots each
-  T *UL = psiL + 5 * SLOT;
-  T *adL = UL + 5 * SLOT;    // alpha_D = D~ (1 - phi)
-  T *aAL = adL + 5 * SLOT;   // alpha_A
-  T *XL = aAL + 5 * SLOT;    // link exchange [row parity][to above, to below][wave][lane]
+  // Field rings, 5 row slots of NZR z layers, stored [slot][layer][field][lane]
+  // so that the four fields of one (row, layer) sit at fixed offsets from one
+  // another and share one address computation.
+  T *XL = sm + 4 * 5 * SLOT;  // link exchange [row parity][to above, to below][wave][lane]
   T *FZ = XL + 4 * NW * 64;  // z-up face flux of each wave's row [wave][lane]
   int8_t *gL = reinterpret_cast<int8_t *>(FZ + NW * 64);  // grains, 5 row slots
 
@@ -168,6 +168,8 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
     return (size_t)j * (size_t)nx;
   };
   auto slot5 = [](int r) { return (r + 10) % 5; };
+  // index of lane 0 of field f at row slot s, z layer zz
+  auto at = [&](int f, int s, int zz) -> int { return ((s * NZR + zz) * 4 + f) * kRS + lane + 1; };
   auto rot_of = [&](int g) -> Rot3<T> {
     Rot3<T> R;
     const T *q = kMulti ? a.rot + 9 * g : a.R;
@@ -175,10 +177,8 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
     for (int i = 0; i < 9; ++i) R.m[i] = q[i];
     return R;
   };
-  // LDS element of field F at row slot s, z layer zz, lane offset dx
-  auto L = [&](const T *F, int s, int zz, int dx) -> T {
-    return F[(s * NZR + zz) * kRS + lane + 1 + dx];
-  };
+  // LDS element of field f at row slot s, z layer zz, lane offset dx
+  auto L = [&](int f, int s, int zz, int dx) -> T { return sm[at(f, s, zz) + dx]; };
 
   // Divergence neighbourhoods: a z-row or y-row beyond a no-flux wall is read
   // as its mirror image (alpha_A included, which the ring waves cannot
@@ -250,12 +250,12 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
     fN = M::tanh_(pN * isq2);
     const int sN = slot5(r);
     {
-      const int o = (sN * NZR + zi) * kRS + lane + 1;
-      psiL[o] = pN;
-      UL[o] = uN;
-      adL[o] = c.D * (T(1) - fN);
-      if (kMulti) gL[o] = (int8_t)gN;
-      if (ring) psiL[(sN * NZR + zih) * kRS + lane + 1] = hN;
+      const int o = at(kPsi, sN, zi);
+      sm[o] = pN;
+      sm[o + (kU - kPsi) * kRS] = uN;
+      sm[o + (kAD - kPsi) * kRS] = c.D * (T(1) - fN);
+      if (kMulti) gL[(sN * NZR + zi) * kRS + lane + 1] = (int8_t)gN;
+      if (ring) sm[at(kPsi, sN, zih)] = hN;
     }
     __syncthreads();
     if constexpr (P == 0) {
@@ -268,11 +268,11 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
 
     if constexpr (P == 1) {
       // only the y face between rows m and m+1 (lower cell (x, m, z))
-      T gyn = (L(psiL, sp1, zi, 0) - L(psiL, s0, zi, 0)) * ih;
-      T gxt = (L(psiL, s0, zi, 1) + L(psiL, sp1, zi, 1) - L(psiL, s0, zi, -1) -
-               L(psiL, sp1, zi, -1)) * qh;
-      T gzt = (L(psiL, s0, zi + 1, 0) + L(psiL, sp1, zi + 1, 0) - L(psiL, s0, zi - 1, 0) -
-               L(psiL, sp1, zi - 1, 0)) * qh;
+      T gyn = (L(kPsi, sp1, zi, 0) - L(kPsi, s0, zi, 0)) * ih;
+      T gxt = (L(kPsi, s0, zi, 1) + L(kPsi, sp1, zi, 1) - L(kPsi, s0, zi, -1) -
+               L(kPsi, sp1, zi, -1)) * qh;
+      T gzt = (L(kPsi, s0, zi + 1, 0) + L(kPsi, sp1, zi + 1, 0) - L(kPsi, s0, zi - 1, 0) -
+               L(kPsi, sp1, zi - 1, 0)) * qh;
       FyS = aniso3<T, 1>(gxt, gyn, gzt, rot_of(gC), c);
       __syncthreads();
       return;
@@ -287,7 +287,7 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
 #pragma unroll
           for (int dx = -1; dx <= 1; ++dx) {
             if (!kShell3 && dx != 0 && dy != 0 && dz != 0) continue;  // corners unused
-            Pn[nb(dx, dy, dz)] = L(psiL, sy[dy + 1], zi + dz, dx);
+            Pn[nb(dx, dy, dz)] = L(kPsi, sy[dy + 1], zi + dz, dx);
           }
       const T p0 = Pn[nb(0, 0, 0)];
       T s1 = T(0), s2 = T(0), s3 = T(0);
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
         T fr = from_right(aA), fl = from_left(aA);
         aA = (x == -1) ? fr : ((x == nx) ? fl : aA);
       }
-      aAL[(s0 * NZR + zi) * kRS + lane + 1] = aA;
+      sm[at(kAA, s0, zi)] = aA;
       aAown[(m + 3) % 3] = aA;
       // dynamic grains: the grain of row m at the next level (a liquid cell,
       // psi < 0, with a solid face neighbour takes the grain of the solid
@@ -414,11 +414,11 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
       // (P == 3: only those towards row q+1, which the first U row needs)
       const int q = m - 1;
       const int sl[3] = {yslot(q - 1), yslot(q), yslot(q + 1)};
-      auto rd = [&](const T *F, int dy, int dz, int dx) -> T {
-        return F[(sl[dy + 1] * NZR + zl[dz + 1]) * kRS + lane + 1 + dx];
+      auto rd = [&](int f, int dy, int dz, int dx) -> T {
+        return sm[at(f, sl[dy + 1], zl[dz + 1]) + dx];
       };
       constexpr bool kFull = P == 4;
-      auto abars = [&](const T *AL, T Pyq) -> Abar9<T> {
+      auto abars = [&](int AL, T Pyq) -> Abar9<T> {
         Abar9<T> o;
         const T a00 = rd(AL, 0, 0, 0), a10 = rd(AL, 1, 0, 0);
         const T a0m = rd(AL, 0, -1, 0), a0p = rd(AL, 0, 1, 0);
@@ -460,7 +460,7 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
         }
         return o;
       };
-      auto diffs = [&](const T *BL) -> Diff9<T> {
+      auto diffs = [&](int BL) -> Diff9<T> {
         Diff9<T> o;
         const T b0 = rd(BL, 0, 0, 0);
         o.N = rd(BL, 1, 0, 0) - b0;
@@ -487,16 +487,16 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
         return o;
       };
       // P_y of row q itself: carried from the row below except at the start
-      auto py_here = [&](const T *AL) -> T {
+      auto py_here = [&](int AL) -> T {
         return c.k1a * rd(AL, 0, 0, 0) +
                c.k1b * (rd(AL, 0, 0, -1) + rd(AL, 0, 0, 1) + rd(AL, 0, -1, 0) + rd(AL, 0, 1, 0));
       };
       if constexpr (!kFull) {
-        PyD = py_here(adL);
-        PyA = py_here(aAL);
+        PyD = py_here(kAD);
+        PyA = py_here(kAA);
       }
-      const Abar9<T> bD = abars(adL, PyD), bA = abars(aAL, PyA);
-      const Diff9<T> dU = diffs(UL), dP = diffs(psiL);
+      const Abar9<T> bD = abars(kAD, PyD), bA = abars(kAA, PyA);
+      const Diff9<T> dU = diffs(kU), dP = diffs(kPsi);
       PyD = bD.Py1;
       PyA = bA.Py1;
       // link values: D~ abar_D dU + abar_A dpsi (D~ is inside alpha_D)
