@@ -582,15 +582,15 @@ namespace {
 template <typename F>
 double time_steps(hipStream_t st, int steps, F run) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.0;
   double out = -1.0;
   float ms = 0.f;
-  if (run(2) == PF_OK && hipEventRecord(e0, st) == hipSuccess && run(steps) == PF_OK &&
+  if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess && run(2) == PF_OK &&
+      hipEventRecord(e0, st) == hipSuccess && run(steps) == PF_OK &&
       hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
       hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
     out = ms * 1e-3;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   return out;
 }
 
