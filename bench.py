@@ -322,7 +322,8 @@ def bench_serve(args):
     80% 2D sides 256..1024, 20% 3D sides 128..192, 2000..10000 steps, FP32)
     under an HBM budget and a cap of 8192 active waves, over 4 streams with
     autotuned geometries; reports p50/p99 time-to-result and throughput, and
-    the same for three baselines on the same trace."""
+    the same for a shortest-job-first variant and three baselines on the same
+    trace."""
     from paper_2110_12448_amd import serve
     from paper_2110_12448_amd import pfiso
     budget = int(args.hbm_budget_gib * (1 << 30))
@@ -344,6 +345,10 @@ def bench_serve(args):
     # completion (no batching, no interleaving) in FP32 and in FP64
     base = {}
     if not args.no_serve_baselines:
+        # the same policy admitting the queued request with the least work first
+        base["serving_shortest_first"] = served(pfiso.PF_F32, hbm_budget_bytes=budget,
+                                                chunk_steps=200, graph_steps=10, order="sjf",
+                                                **policy)[1]
         base["all_admitted_sharing_f32"] = served(pfiso.PF_F32, hbm_budget_bytes=budget,
                                                   chunk_steps=200, graph_steps=10,
                                                   autotune_steps=5)[1]

@@ -84,6 +84,10 @@ def estimated_waves(prob: dict) -> int:
     return col * -(-prob["nz"] // zt) * (zt + 2)
 
 
+def _work(r: Request) -> int:
+    return int(r.problem["nx"]) * int(r.problem["ny"]) * int(r.problem["nz"]) * int(r.steps)
+
+
 def _shape_class(prob: dict, precision: int):
     return (prob["dim"], prob["nx"], prob["ny"], prob["nz"], precision,
             int(prob.get("antitrapping", 0)), int(prob.get("two_point", 0)))
@@ -107,7 +111,7 @@ class Server:
     def __init__(self, hbm_budget_bytes: int, chunk_steps: int = 200, device: str = "cuda:0",
                  keep_fields: bool = False, graph_steps: int = 0, batching: bool = True,
                  progress: int = 0, max_waves: Optional[int] = None, streams: int = 1,
-                 autotune_steps: int = 0):
+                 autotune_steps: int = 0, order: str = "fifo"):
         """max_waves: admit a request only while the active solves occupy fewer
         waves than this (estimated_waves; None: the HBM budget alone decides).
         streams: HIP streams the solves are spread over (batched solves share
@@ -116,7 +120,11 @@ class Server:
         autotune_steps > 0: each unbatched solve takes the launch geometry
         pf_autotune finds for its shape class (timed once per class, on the
         first admission), and each batch kind the segment length
-        pf_batch_autotune finds for the first batch of 4 or more solves."""
+        pf_batch_autotune finds for the first batch of 4 or more solves.
+        order: "fifo" admits in arrival order, "sjf" the least work first."""
+        if order not in ("fifo", "sjf"):
+            raise ValueError(order)
+        self.order = order
         self.progress = int(progress)    # > 0: a line on stderr every `progress` results
         self.max_waves = max_waves
         self.n_streams = max(1, int(streams))
@@ -158,7 +166,10 @@ class Server:
             while pending and pending[0].arrival <= t:
                 queue.append(pending.pop(0))
             # admission by HBM budget, arrival order (a request larger than
-            # the whole budget is admitted alone)
+            # the whole budget is admitted alone); "sjf" admits the queued
+            # request with the least work (cells x steps) first
+            if self.order == "sjf":
+                queue.sort(key=lambda q: (_work(q), q.arrival, q.rid))
             while queue:
                 r = queue[0]
                 need = workspace_bytes(r.problem, r.precision)

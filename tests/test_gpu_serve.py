@@ -7,7 +7,8 @@ pytestmark = pytest.mark.gpu
 
 
 POLICIES = [dict(), dict(max_waves=64, streams=3, autotune_steps=2),
-            dict(streams=2, autotune_steps=2, batching=False)]
+            dict(streams=2, autotune_steps=2, batching=False),
+            dict(max_waves=200, streams=2, order="sjf")]
 
 
 @pytest.mark.parametrize("policy", range(len(POLICIES)))

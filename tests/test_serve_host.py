@@ -1,0 +1,40 @@
+"""Host-side logic of the request loop (no GPU): the seeded trace, the wave
+estimate used by the admission cap, and the policy switches."""
+import pytest
+
+from paper_2110_12448_amd import serve
+from paper_2110_12448_amd import workloads as wl
+
+
+def test_trace_is_seeded_and_mixed():
+    a = serve.poisson_trace(n=24, seed=5)
+    b = serve.poisson_trace(n=24, seed=5)
+    assert [(r.arrival, r.steps, r.problem["nx"]) for r in a] == \
+           [(r.arrival, r.steps, r.problem["nx"]) for r in b]
+    assert all(x.arrival < y.arrival for x, y in zip(a, a[1:]))
+    dims = {r.problem["dim"] for r in a}
+    assert dims == {2, 3}
+    for r in a:
+        assert 2000 <= r.steps <= 10000
+        if r.problem["dim"] == 2:
+            assert r.problem["nx"] % 64 == 0 and 256 <= r.problem["nx"] <= 1024
+        else:
+            assert r.problem["nx"] in (128, 160, 192)
+
+
+@pytest.mark.parametrize("shape,want", [
+    ((256, 256), 5 * 32),                        # 2D: 60-column strips x 8-row segments
+    ((1024, 1024), 18 * 128),
+    ((128, 128, 128), 3 * 4 * 22 * 8),           # 3D, few workgroups: 6 z rows in 8 waves
+    ((256, 256, 256), 5 * 8 * 19 * 16),          # 3D, many: 14 z rows in 16 waves
+])
+def test_estimated_waves(shape, want):
+    pr = wl.problem(len(shape), shape, noise=0.0)
+    assert serve.estimated_waves(pr) == want
+
+
+def test_policy_switches_validated():
+    with pytest.raises(ValueError):
+        serve.Server(1 << 30, order="lifo")
+    s = serve.Server(1 << 30, order="sjf", max_waves=8192, streams=4, autotune_steps=5)
+    assert s.order == "sjf" and s.n_streams == 4 and s.max_waves == 8192
