@@ -198,7 +198,9 @@ int pf_frame_state(pf_solver *s, int64_t *shift, int32_t *pending);
 int pf_tune(pf_solver *s, int32_t rows_per_segment, int32_t z_tile);
 
 /* The launch geometry in use (the library's default for the lattice and
- * precision until pf_tune or pf_autotune changes it); z_tile is 1 in 2D. */
+ * precision until pf_tune or pf_autotune changes it); z_tile is 1 in 2D.
+ * Either pointer may be NULL.  PF_ERR_ARG for a NULL solver.  (Launch
+ * geometry is not part of the paper's method: results never depend on it.) */
 int pf_geometry(pf_solver *s, int32_t *rows_per_segment, int32_t *z_tile);
 
 /* Tile autotuner: time each candidate launch geometry (2D: rows per segment
@@ -211,7 +213,9 @@ int pf_geometry(pf_solver *s, int32_t *rows_per_segment, int32_t *z_tile);
  * of the workspace (one extra workspace allocated and freed here), so the
  * solve itself neither advances nor changes; results never depend on the
  * choice.  Synchronises.  seg and ztile (either may be NULL) receive the
- * choice (ztile 1 in 2D).  PF_ERR_OOM when the scratch copy does not fit. */
+ * choice (ztile 1 in 2D).  PF_ERR_ARG for a NULL solver or steps_per_trial
+ * < 1, PF_ERR_OOM when the scratch copy does not fit, PF_ERR_DEVICE when a
+ * trial launch fails (the solve is then unchanged). */
 int pf_autotune(pf_solver *s, int32_t steps_per_trial, int32_t *seg, int32_t *ztile);
 
 /* Release the solver (and its workspace if the library allocated it). */
@@ -248,8 +252,9 @@ int pf_batch_use_graph(pf_batch *b, int32_t steps_per_graph);
  * then rebuild the batch with the choice (kept until the batch is destroyed;
  * it overrides the members' own pf_tune settings inside the batch only).  The
  * members do not advance.  Synchronises.  *seg (may be NULL) receives the
- * choice, 0 meaning each member's own segment length.  PF_ERR_OOM when the
- * copies do not fit. */
+ * choice, 0 meaning each member's own segment length.  PF_ERR_ARG for a
+ * NULL batch or steps_per_trial < 1, PF_ERR_OOM when the copies do not fit,
+ * PF_ERR_DEVICE when a trial launch fails. */
 int pf_batch_autotune(pf_batch *b, int32_t steps_per_trial, int32_t *seg);
 
 /* Release the batch (not its solvers). */
