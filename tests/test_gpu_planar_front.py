@@ -15,7 +15,7 @@ A2 = 47.0 / 75.0
 K, EPS4, D, VP, LT, H_DOMAIN, YF0 = 0.15, 0.02, 2.0, 0.05, 400.0, 320.0, 40.0
 
 
-def planar_problem(h=0.8, nx=2):
+def planar_problem(h=0.8, nx=4):
     ny = int(round(H_DOMAIN / h))
     y = np.arange(ny) * h
     psi0 = np.repeat((-(y - YF0) / (1.0 + EPS4))[:, None], nx, axis=1)
