@@ -627,6 +627,15 @@ def main():
         ophi = np.tanh(opsi / math.sqrt(2.0))
         err = {"steps": nst, "max_abs_dphi": float(np.max(np.abs(phi - ophi))),
                "max_abs_dU": float(np.max(np.abs(U - oU)))}
+        # the FP32 storage floor beside it: the oracle rounding its stored psi
+        # and U to FP32 after every step, against the plain FP64 oracle
+        import oracle
+        print("fp32 storage floor: %d oracle steps" % nst, file=sys.stderr, flush=True)
+        rpsi, rU, _ = oracle.step(oracle.Params.from_problem(pr, round_f32=1), pr["psi0"],
+                                  pr["U0"], pr["grain"], nst)
+        err["fp32_storage_floor"] = {
+            "max_abs_dphi": float(np.max(np.abs(np.tanh(rpsi / math.sqrt(2.0)) - ophi))),
+            "max_abs_dU": float(np.max(np.abs(rU - oU)))}
 
     out = {
         "metric": "phi+U cell-updates/s",
