@@ -8,7 +8,8 @@ pytestmark = pytest.mark.gpu
 
 POLICIES = [dict(), dict(max_waves=64, streams=3, autotune_steps=2),
             dict(streams=2, autotune_steps=2, batching=False),
-            dict(max_waves=200, streams=2, order="sjf")]
+            dict(max_waves=200, streams=2, order="sjf"),
+            dict(streams=2, autotune_steps=2)]   # with mixed precisions
 
 
 @pytest.mark.parametrize("policy", range(len(POLICIES)))
@@ -18,6 +19,10 @@ def test_served_equals_alone(policy):
     from paper_2110_12448_amd import pfiso, serve
     reqs = serve.poisson_trace(n=10, rate=200.0, seed=9, frac_3d=0.3, steps=(20, 60),
                                sides_2d=(64, 192), sides_3d=(16, 24))
+    if policy == len(POLICIES) - 1:
+        # mixed precisions: FP64 and FP32 2D solves form separate batches
+        for r in reqs[1::2]:
+            r.precision = pfiso.PF_F64
     one = max(serve.workspace_bytes(r.problem, r.precision) for r in reqs)
     srv = serve.Server(hbm_budget_bytes=3 * one, chunk_steps=16, keep_fields=True, graph_steps=2,
                        **POLICIES[policy])
