@@ -89,6 +89,10 @@ EDGE = [
     (64, 64, (0, 0, 0), "frozen", wl.STD_2D, 1, 17.0, 0.02),
     (121, 50, (1, 1, 1), "isothermal", (0.5, 0.5, 0.0), 2, 40.0, 0.04),
     (7, 200, (0, 0, 0), "frozen", wl.ISO_2D, 1, 45.0, 0.02),
+    # strip boundaries: two full 60-column strips, and one column past three
+    # (four balanced strips of 46, the last one 43 wide)
+    (120, 33, (1, 0, 0), "frozen", wl.ISO_2D, 1, 25.0, 0.02),
+    (181, 20, (0, 0, 0), "isothermal", wl.ISO_2D, 2, 5.0, 0.03),
 ]
 
 
