@@ -151,6 +151,28 @@ def test_directional_full_size_fp32():
     assert abs(tip["y_frame"] - ot["y"]) < 1e-3
 
 
+def test_directional_full_size_tip_fp32_vs_fp64_20k_steps():
+    """The benchmark's whole 1024 x 2048 moving-frame solve (2 x 10^4 steps,
+    the frame moving after about 1.2 x 10^4): the FP32 tip within 0.05 W of
+    the FP64 one.  The FP64 GPU path stands in for the oracle here (it matches
+    the oracle to ~1e-15 in every parity case, and the oracle would need
+    minutes for this run); the frame shifts agree."""
+    pf = _pf()
+    pr = wl.config_directional_2d()
+    out = {}
+    for prec in (pf.PF_F64, pf.PF_F32):
+        print("gpu case: 1024x2048 directional prec=%d steps=20000" % prec, flush=True)
+        s = pf.Solver(pr, precision=prec)
+        s.step(20000)
+        out[prec] = s.tip_state()
+        s.close()
+    t64, t32 = out[pf.PF_F64], out[pf.PF_F32]
+    print({k: (t64[k], t32[k]) for k in ("y_lab", "x", "frame_shift", "solid_fraction")})
+    assert t64["frame_shift"] > 100 and abs(t32["frame_shift"] - t64["frame_shift"]) <= 1
+    assert abs(t32["y_lab"] - t64["y_lab"]) <= 0.05
+    assert abs(t32["solid_fraction"] - t64["solid_fraction"]) <= 1e-4
+
+
 def test_tip_after_10k_steps():
     """Tip within 0.05 W of the oracle after 10^4 steps (128 x 128, frame at
     row 64); oracle values stored by tests/golden/make_tip_golden.py."""
