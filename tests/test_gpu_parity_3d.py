@@ -139,3 +139,24 @@ def test_polycrystal_441_size_fp32():
     ophi, oU, _, st, p = run_oracle(pr, 3)
     phi, U, psi, tip, _ = run_gpu(pr, 0, 3)
     assert max(_cmp(phi, ophi), _cmp(U, oU)) <= TOL_F32
+
+
+def test_polycrystal_full_run_fp32_vs_fp64():
+    """The 256^3 polycrystal for the 5000 steps of its workload: the FP32 tip
+    within 0.05 W of the FP64 one and the solid fractions within 1e-4 (the
+    FP64 GPU path stands in for the oracle, as in the 2D full-run test)."""
+    pf = _pf()
+    pr = wl.config_polycrystal_3d()
+    out = {}
+    for prec in (pf.PF_F64, pf.PF_F32):
+        print("gpu case: 256^3 polycrystal prec=%d steps=5000" % prec, flush=True)
+        s = pf.Solver(pr, precision=prec)
+        for _ in range(5):
+            s.step(1000)
+            s.synchronize()
+        out[prec] = s.tip_state()
+        s.close()
+    t64, t32 = out[pf.PF_F64], out[pf.PF_F32]
+    print({k: (t64[k], t32[k]) for k in ("y_lab", "x", "z", "solid_fraction")})
+    assert t64["found"] and abs(t32["y_lab"] - t64["y_lab"]) <= 0.05
+    assert abs(t32["solid_fraction"] - t64["solid_fraction"]) <= 1e-4
