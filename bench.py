@@ -260,6 +260,12 @@ def _copy_GBs(nbytes=1 << 30, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+# counter summary of the diffusion-only kernel on 8192^2 (HBM regime)
+DIFFUSION_COUNTERS = dict(
+    sources=["paper_2110_12448_amd/csrc/step2d.hip", "paper_2110_12448_amd/csrc/pf_device.hpp"],
+    counters="profiles/step2d_diffusion_8192x8192_counters.json")
+
+
 def bench_diffusion(args):
     """The diffusion-only step (psi held, U by D~ div[(1-phi) grad U]): the same
     16 bytes per cell as the full step with a fraction of its arithmetic, on
@@ -270,14 +276,22 @@ def bench_diffusion(args):
     steps = args.steps or 400
     warm = args.warmup if args.warmup is not None else 20
     nl = args.launch_sample or 100
+    if "8192x8192" not in args.diffusion_sizes.split(","):
+        print("diffusion2d reports the 8192x8192 lattice: include it in --diffusion-sizes",
+              file=sys.stderr)
+        sys.exit(2)
     res = {}
-    for label, pr in (("8192x8192", wl.config_directional_2d(nx=8192, ny=8192)),
-                      ("1024x2048", wl.config_directional_2d())):
+    geo = None
+    sizes = [("8192x8192", wl.config_directional_2d(nx=8192, ny=8192)),
+             ("1024x2048", wl.config_directional_2d())]
+    for label, pr in [z for z in sizes if z[0] in args.diffusion_sizes.split(",")]:
         cells = pr["nx"] * pr["ny"]
         s = pfiso.Solver(pr, precision=pfiso.PF_F32)
         st = s.stream
-        print("bench: diffusion2d %s FP32, warmup %d, steps %d" % (label, warm, steps),
-              file=sys.stderr, flush=True)
+        if label == "8192x8192":
+            geo = s.geometry()
+        print("bench: diffusion2d %s FP32, warmup %d, steps %d, geometry %s" % (
+            label, warm, steps, s.geometry()), file=sys.stderr, flush=True)
         s.step_diffusion(warm)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -296,22 +310,29 @@ def bench_diffusion(args):
         torch.cuda.synchronize()
         kern_ms = sum(a.elapsed_time(b) for a, b in evs) / nl
         s.close()
+        # the timed region is back-to-back launches of this one kernel: its
+        # average is the kernel's average launch duration
         res[label] = {"ms_per_step": ms, "cell_updates_per_s": cells / (ms * 1e-3),
-                      "kernel_ms": round(kern_ms, 5),
-                      "algorithmic_GBs": round(ALG_BYTES_2D_F32 * cells / (kern_ms * 1e-3) / 1e9, 1)}
+                      "kernel_ms_isolated_launch": round(kern_ms, 5),
+                      "algorithmic_GBs": round(ALG_BYTES_2D_F32 * cells / (ms * 1e-3) / 1e9, 1)}
     copy = _copy_GBs()
     big = res["8192x8192"]
     gbs = big["algorithmic_GBs"]
+    ctr = load_counters(DIFFUSION_COUNTERS, geo)
     out = {"metric": "phi+U cell-updates/s", "value": big["cell_updates_per_s"],
            "unit": "cell-updates/s", "n_gpus": 1, "steps": steps, "warmup": warm,
            "ms_per_step": big["ms_per_step"], "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "diffusion-only step (psi held, U by the shell divergence of "
-                                  "Eq. PF_b), 8192x8192 FP32, 16 B per cell as the full step"},
+                                  "Eq. PF_b), 8192x8192 FP32, 16 B per cell as the full step",
+                      "rows_per_segment": geo[0], "z_tile": geo[1]},
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                        "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
+                        "frac": round(gbs / PEAK_HBM_GBS, 4),
+                        "traffic": None if ctr is None else ctr["hbm_bytes_per_launch"],
                         "kernel": "step2d_kernel<float,frozen,frame,diffusion-only>",
-                        "kernel_ms": big["kernel_ms"], "copy_GBs_measured": round(copy, 1),
+                        "kernel_ms": round(big["ms_per_step"], 5),
+                        "counters_kernel_ns": None if ctr is None else ctr["avg_duration_ns"],
+                        "copy_GBs_measured": round(copy, 1),
                         "frac_of_copy": round(gbs / copy, 4)},
            "sizes": res}
     print(json.dumps(out))
@@ -508,6 +529,8 @@ def main():
     ap.add_argument("--no-serve-baselines", action="store_true",
                     help="serve: skip the one-at-a-time FP32/FP64 runs of the same trace")
     ap.add_argument("--hbm-budget-gib", type=float, default=2.0)
+    ap.add_argument("--diffusion-sizes", default="8192x8192,1024x2048",
+                    help="diffusion2d: lattices to run (8192x8192 is the reported one)")
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the untimed extras: CPU oracle baseline, error against the "
                          "oracle and (directional2d) the growth observables")
