@@ -286,7 +286,9 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
           aA = (x == -1) ? fr : ((x == nx) ? fl : aA);
         }
         aAC = aA;
-        if (a.bcy == PF_BC_NOFLUX) {  // mirrored rows copy their image
+        // mirrored rows copy their image (rows 0 and ny, never met inside the
+        // unrolled steady state: phase 5)
+        if (P != 5 && a.bcy == PF_BC_NOFLUX) {
           if (m == 0) aAS = aAC;
           if (m == ny) aAC = aAS;
         }
@@ -328,7 +330,7 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
           fE += fEA;
           fN += fNA;
         }
-        if constexpr (P == 4) {
+        if constexpr (P >= 4) {
           T div = c.cT * (fE - from_left(fE) + fN - cN);
           T rU = (div + sq2 * aAS) * M::rcp(T(1) + c.k - c.omk * fS);
           if (out_lane) a.U_out[(size_t)q * (size_t)nx + (size_t)x] = uS + c.dt * rU;
@@ -390,7 +392,7 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
             fNA *= invN;
             d1A *= invNE;
             d2A *= from_left(invNE);
-            if constexpr (P == 4) {  // face (1/2, 0)
+            if constexpr (P >= 4) {  // face (1/2, 0)
               T a1 = pCE - pB1, b1 = pB1E - pC;
               T a2 = pCE2 - pB1W, b2 = pB1E2 - pCW;
               T a3 = pNE - pB2, b3 = pB2E - pN;
@@ -410,7 +412,7 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
           }
         }
 
-        if constexpr (P == 4) {
+        if constexpr (P >= 4) {
           T div = c.cD1 * (fE - from_left(fE) + fN - cN) +
                   c.cD2 * (d1 + d2 - from_left(c1) - from_right(c2));
           // the held psi has no anti-trapping current and no source
@@ -425,21 +427,24 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
     using I2 = std::integral_constant<int, 2>;
     using I3 = std::integral_constant<int, 3>;
     using I4 = std::integral_constant<int, 4>;
+    using I5 = std::integral_constant<int, 5>;  // phase 4 on rows 1..ny-1
     iter(I0{}, y0 - 2);
     iter(I1{}, y0 - 1);
     iter(I2{}, y0);
     iter(I3{}, y0 + 1);
     // steady state unrolled by 6, a multiple of every register-rotation
     // period (3 for the row window, the grains and the loads in flight, 2 for
-    // alpha_A, 1 for the carries), so the rotation costs no register moves
+    // alpha_A, 1 for the carries), so the rotation costs no register moves.
+    // Its psi rows m = r - 1 run from y0 + 1 to at most ye - 1, so none is
+    // row 0 or ny (the last row of a segment goes to the loop below).
     int r = y0 + 2;
-    for (; r + 5 <= ye + 1; r += 6) {
-      iter(I4{}, r);
-      iter(I4{}, r + 1);
-      iter(I4{}, r + 2);
-      iter(I4{}, r + 3);
-      iter(I4{}, r + 4);
-      iter(I4{}, r + 5);
+    for (; r + 5 <= ye; r += 6) {
+      iter(I5{}, r);
+      iter(I5{}, r + 1);
+      iter(I5{}, r + 2);
+      iter(I5{}, r + 3);
+      iter(I5{}, r + 4);
+      iter(I5{}, r + 5);
     }
     for (; r <= ye + 1; ++r) iter(I4{}, r);
     if (kReduce) over_any = __any(over);
