@@ -28,7 +28,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
-PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector (published)
+PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector (published; counts packed FP32 FMAs)
+PEAK_FP32_NONPACKED_TFLOPS = 78.6  # the same vector units issuing one FP32 FMA per lane
 # FP32 operations per cell-update of the 2D step as written in step2d.hip
 # (FMA = 2, each transcendental = 1; index math, selects and cross-lane moves
 # not counted): tanh 6, y-face flux 30, psi rate 112 (L 10, G 9, centre a_s
@@ -617,6 +618,7 @@ def main():
     traffic = None if ctr is None else ctr["hbm_bytes_per_launch"]
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
+                "frac_of_nonpacked_fp32": round(achieved_tflops / PEAK_FP32_NONPACKED_TFLOPS, 4),
                 "traffic": traffic,
                 "kernel": wk["kernel"], "kernel_ms": round(step_kernel_ms, 5),
                 "kernel_ms_isolated_launch": round(kern_ms, 5),
