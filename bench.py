@@ -167,6 +167,17 @@ def bench_batched(args):
            "default_segment_value": cells * steps / t_default,
            "one_at_a_time_f32": cells * solo_steps / t32,
            "one_at_a_time_f64": cells * (solo_steps // 2) / t64}
+    # the batched step kernel is the same 2D step body: 209 flops and 16 B of
+    # algorithmic traffic per cell-update
+    tfl = ALG_FLOPS_2D * batched / 1e12
+    gbs = ALG_BYTES_2D_F32 * batched / 1e9
+    out["roofline"] = {"bound": "alu", "achieved": round(tfl, 3), "peak": PEAK_FP32_TFLOPS,
+                       "unit": "TFLOP/s", "frac": round(tfl / PEAK_FP32_TFLOPS, 4),
+                       "frac_of_nonpacked_fp32": round(tfl / PEAK_FP32_NONPACKED_TFLOPS, 4),
+                       "traffic": None, "kernel": "batch2d_kernel<float,frozen>",
+                       "kernel_ms": round(t / steps * 1e3, 5),
+                       "hbm_algorithmic_GBs": round(gbs, 1),
+                       "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)}
     print(json.dumps(out))
 
 
