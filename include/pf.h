@@ -230,7 +230,9 @@ void pf_destroy(pf_solver *s);
  * (all frozen or all isothermal, all with or without the moving frame, all
  * single- or all multi-grain), on the approximated current with shell
  * divergences (the defaults) and bound to one stream.  Results are bitwise
- * those of stepping each solve on its own with the same launch geometry. */
+ * those of stepping each solve on its own with the same launch geometry.  A
+ * batch of one solver is valid: it replays a single small solve from a graph,
+ * without a launch per step. */
 typedef struct pf_batch pf_batch;
 
 /* Build a batch over n solvers (the caller keeps the solvers). */

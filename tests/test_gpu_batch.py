@@ -91,3 +91,10 @@ def test_batch_graph_replays(graph, prec):
 
 def test_batch_interleaved_single_steps():
     check_batch(problems(), 1, [("b", 10), ("s", 3, 4), ("b", 10), ("s", 1, 1), ("b", 3)])
+
+
+def test_batch_of_one_replays_a_single_solve():
+    """A single small solve replayed from a graph (6-launch epochs, moving
+    frame) equals the same solve stepped launch by launch."""
+    prs = problems(frame=True, thermal="frozen")[:1]
+    check_batch(prs, 0, [("b", 37), ("s", 0, 2), ("b", 12)], graph=6)
