@@ -46,26 +46,33 @@ int default_seg2d(int nx, int ny) {
   long long seg = strips * ny / 4608;
   return (int)(seg < 8 ? 8 : (seg > 32 ? 32 : seg));
 }
-// Default 3D geometry.  z rows per workgroup: in FP32, 14 (16 waves, the most
+// Default 3D geometry.  FP32: 14 z rows per workgroup (16 waves, the most
 // one workgroup holds: one workgroup per CU at the kernel's ~110 VGPRs, ring
-// waves costing 16/14 instead of 8/6) when that still gives at least 400
-// workgroups with 32-row segments, else 6 (two 8-wave workgroups per CU);
-// 2 in FP64 (4 waves, the thread limit of its launch bounds).  Rows per
-// segment: the longest of 32, 16, 8 that keeps 400 workgroups, else 8.  From
-// a sweep of cubes 96^3..512^3: 42.2 G cell-updates/s on 256^3 with (32, 14)
-// against 39.5 with (32, 6); 35.0 on 192^3 with (32, 6) against 27.1 with
-// (32, 14).  pf_autotune refines it per lattice.
+// waves costing 16/14 instead of 8/6 for two 6-row workgroups), with 32-row
+// segments when that gives at least 400 workgroups, else 16-row ones when
+// that gives 200, else 8.  FP64: 2 z rows (4 waves, the thread limit of its
+// launch bounds) and the longest of 32, 16, 8 rows that keeps 400
+// workgroups.  From a sweep of cubes 96^3..512^3 (one run each), this is
+// within 14-18% of the best tile on 96^3 and 160^3 and within 7% elsewhere
+// (128^3: 28.3 G cell-updates/s with (16, 14) against 19.9 with (16, 6);
+// 256^3: 42.2 with (32, 14) against 39.5 with (32, 6)); pf_autotune refines
+// it per lattice.
 std::pair<int, int> default_geom3d(const pf_params *p) {
   auto blocks = [&](int seg, int zt) { return geom3d(p->nx, p->ny, p->nz, seg, zt).blocks; };
-  int zt = 2;
-  if (p->precision != PF_F64) zt = blocks(32, 14) >= 400 ? 14 : 6;
-  zt = std::min(zt, std::max(1, p->nz));  // no idle z waves on thin lattices
+  const bool f64 = p->precision == PF_F64;
+  const int zt = std::min(f64 ? 2 : 14, std::max(1, p->nz));  // no idle z waves on thin lattices
   int seg = 8;
-  for (int s : {32, 16})
-    if (blocks(s, zt) >= 400) {
-      seg = s;
-      break;
-    }
+  if (f64) {
+    for (int s : {32, 16})
+      if (blocks(s, zt) >= 400) {
+        seg = s;
+        break;
+      }
+  } else if (blocks(32, zt) >= 400) {
+    seg = 32;
+  } else if (blocks(16, zt) >= 200) {
+    seg = 16;
+  }
   return {seg, zt};
 }
 constexpr size_t kMaxLds3D = 163840;  // LDS one gfx950 workgroup may allocate

@@ -73,15 +73,17 @@ def _batchable(prob: dict) -> bool:
 def estimated_waves(prob: dict) -> int:
     """Waves one step launch of this solve occupies at the library's default
     geometry (60 output columns per wave; 2D segments of about 8 rows; 3D
-    segments of 32 rows and workgroups of 14 z rows in 16 waves, or of 6 z
-    rows in 8 waves when that leaves fewer than 400 workgroups): the measure
-    of how much of the chip a solve fills on its own."""
+    workgroups of 14 z rows in 16 waves, on segments of 32 rows when that
+    gives 400 workgroups, else 16 rows when that gives 200, else 8): the
+    measure of how much of the chip a solve fills on its own."""
     strips = -(-prob["nx"] // 60)
     if prob["dim"] == 2:
         return strips * -(-prob["ny"] // 8)
-    col = strips * -(-prob["ny"] // 32)
-    zt = 14 if col * -(-prob["nz"] // 14) >= 400 else 6
-    return col * -(-prob["nz"] // zt) * (zt + 2)
+    zt = min(14, prob["nz"])
+    tiles = -(-prob["nz"] // zt)
+    blocks = {s: strips * -(-prob["ny"] // s) * tiles for s in (32, 16, 8)}
+    seg = 32 if blocks[32] >= 400 else (16 if blocks[16] >= 200 else 8)
+    return blocks[seg] * (zt + 2)
 
 
 def _work(r: Request) -> int:

@@ -25,8 +25,8 @@ def test_trace_is_seeded_and_mixed():
 @pytest.mark.parametrize("shape,want", [
     ((256, 256), 5 * 32),                        # 2D: 60-column strips x 8-row segments
     ((1024, 1024), 18 * 128),
-    ((128, 128, 128), 3 * 4 * 22 * 8),           # 3D, few workgroups: 6 z rows in 8 waves
-    ((256, 256, 256), 5 * 8 * 19 * 16),          # 3D, many: 14 z rows in 16 waves
+    ((128, 128, 128), 3 * 8 * 10 * 16),          # 3D, few workgroups: 16-row segments
+    ((256, 256, 256), 5 * 8 * 19 * 16),          # 3D, many: 32-row segments, 14 z rows
 ])
 def test_estimated_waves(shape, want):
     pr = wl.problem(len(shape), shape, noise=0.0)
