@@ -33,6 +33,7 @@
 // dynamic grains it writes the next level's grain map.  No-flux walls: psi, U and phi
 // are read through the mirror map, and every field beyond a wall is read at
 // its image (alpha_A of a mirrored cell included).
+#include <atomic>
 #include <type_traits>
 
 #include "pf_device.hpp"
@@ -591,15 +592,24 @@ size_t step3d_lds_bytes(int ztile, size_t elem) {
 }
 
 // Launch one instantiation; workgroups above 64 KB of LDS need the kernel's
-// dynamic-LDS limit raised once (gfx950 allows up to 160 KB per workgroup).
+// dynamic-LDS limit raised once per device (gfx950 allows up to 160 KB per
+// workgroup).  Safe to call from several host threads.
+constexpr int kMaxDevices = 64;
 template <typename T, bool F, bool R, bool MU, bool S3>
 hipError_t launch3(const Step3DArgs<T> &a, dim3 grid, dim3 block, size_t lds, hipStream_t st) {
-  static size_t allowed = 65536;
-  if (lds > allowed) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step3d_kernel<T, F, R, MU, S3>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  // dynamic-LDS limit already raised for this instantiation, per device
+  static std::atomic<size_t> allowed[kMaxDevices];
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  if (lds > 65536 && lds > allowed[dev].load(std::memory_order_relaxed)) {
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step3d_kernel<T, F, R, MU, S3>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    allowed = lds;
+    size_t cur = allowed[dev].load(std::memory_order_relaxed);
+    while (cur < lds && !allowed[dev].compare_exchange_weak(cur, lds)) {
+    }
   }
   hipLaunchKernelGGL((step3d_kernel<T, F, R, MU, S3>), grid, block, lds, st, a);
   return hipSuccess;
