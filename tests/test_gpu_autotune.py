@@ -70,8 +70,8 @@ def test_autotune_rejects_bad_trial_count():
     s.close()
 
 
-@pytest.mark.parametrize("frame,graph", [(False, 0), (True, 6)])
-def test_batch_autotune(frame, graph):
+@pytest.mark.parametrize("frame,graph,prec", [(False, 0, 0), (True, 6, 0), (True, 6, 1)])
+def test_batch_autotune(frame, graph, prec):
     pf = _pf()
     sizes = [(64, 64), (97, 130), (200, 61), (31, 40)]
     prs = []
@@ -80,8 +80,8 @@ def test_batch_autotune(frame, graph):
         if frame:
             kw.update(thermal="frozen", frame=1, shift_row=max(2, ny // 5))
         prs.append(wl.problem(2, (nx, ny), **kw))
-    print("batch autotune frame=%d graph=%d" % (frame, graph), flush=True)
-    ss = [pf.Solver(pr, precision=pf.PF_F32) for pr in prs]
+    print("batch autotune frame=%d graph=%d prec=%d" % (frame, graph, prec), flush=True)
+    ss = [pf.Solver(pr, precision=prec) for pr in prs]
     b = pf.Batch(ss, graph_steps=graph)
     b.step(6)
     pre = [_state(s) for s in ss]
@@ -90,7 +90,7 @@ def test_batch_autotune(frame, graph):
     assert all(_same(_state(s), p) for s, p in zip(ss, pre))
     b.step(18)
     for pr, s in zip(prs, ss):
-        r = pf.Solver(pr, precision=pf.PF_F32)
+        r = pf.Solver(pr, precision=prec)
         r.step(24)
         assert _same(_state(s), _state(r))
         r.close()
