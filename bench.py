@@ -181,6 +181,12 @@ def bench_batched(args):
     print(json.dumps(out))
 
 
+# counter summary of the S_{2,1} (full current, App. B) step kernel on 781^2
+SCHEMES_COUNTERS = dict(
+    sources=["paper_2110_12448_amd/csrc/step2d.hip", "paper_2110_12448_amd/csrc/pf_device.hpp"],
+    counters="profiles/step2d_S21_781sq_counters.json")
+
+
 def bench_schemes(args):
     """The three 2D schemes of Table 1 on the isothermal free-growth run
     (781^2, 20345 steps, FP32): the whole run timed per scheme, with the
@@ -193,13 +199,20 @@ def bench_schemes(args):
     warm = args.warmup if args.warmup is not None else 200
     nl = args.launch_sample or 200
     out_s = {}
-    for name in ("S10", "S21", "Sbar21"):
+    names = args.schemes.split(",")
+    if "S21" not in names:
+        print("schemes2d reports S21: include it in --schemes", file=sys.stderr)
+        sys.exit(2)
+    geo = None
+    for name in [n for n in ("S10", "S21", "Sbar21") if n in names]:
         pr = wl.config_isothermal_2d(**wl.SCHEMES_2D[name])
         cells = pr["nx"] * pr["ny"]
         s = pfiso.Solver(pr, precision=pfiso.PF_F32)
         st = s.stream
-        print("bench: schemes2d %s %dx%d FP32, warmup %d, steps %d" %
-              (name, pr["nx"], pr["ny"], warm, steps), file=sys.stderr, flush=True)
+        if name == "S21":
+            geo = s.geometry()
+        print("bench: schemes2d %s %dx%d FP32, warmup %d, steps %d, geometry %s" %
+              (name, pr["nx"], pr["ny"], warm, steps, s.geometry()), file=sys.stderr, flush=True)
         s.step(warm)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -219,15 +232,22 @@ def bench_schemes(args):
         kern_ms = sum(a.elapsed_time(b) for a, b in evs) / nl
         tip = s.tip_state()
         s.close()
-        tf = SCHEME_FLOPS_2D[name] * cells / (kern_ms / 1e3) / 1e12
+        # launches run back to back in the timed run: its average step is the
+        # kernel's average duration (isolated launches add event overhead)
+        step_ms = run_s * 1e3 / steps
+        tf = SCHEME_FLOPS_2D[name] * cells / (step_ms / 1e3) / 1e12
         out_s[name] = {"run_s": run_s, "cell_updates_per_s": cells * steps / run_s,
-                       "kernel_ms": round(kern_ms, 5), "flops_per_cell": SCHEME_FLOPS_2D[name],
+                       "kernel_ms": round(step_ms, 5),
+                       "kernel_ms_isolated_launch": round(kern_ms, 5),
+                       "flops_per_cell": SCHEME_FLOPS_2D[name],
                        "achieved_TFLOPs": round(tf, 3),
                        "alu_frac": round(tf / PEAK_FP32_TFLOPS, 4),
                        "tip_y": tip["y_lab"], "solid_fraction": tip["solid_fraction"],
                        "paper_p100_run_s": PAPER_TABLE1_S[name]}
-    for name in out_s:
-        out_s[name]["time_vs_S10"] = round(out_s[name]["run_s"] / out_s["S10"]["run_s"], 3)
+    if "S10" in out_s:
+        for name in out_s:
+            out_s[name]["time_vs_S10"] = round(out_s[name]["run_s"] / out_s["S10"]["run_s"], 3)
+    ctr = load_counters(SCHEMES_COUNTERS, geo)
     pr = wl.config_isothermal_2d(**wl.SCHEMES_2D["S21"])
     cells = pr["nx"] * pr["ny"]
     main_s = out_s["S21"]
@@ -243,11 +263,15 @@ def bench_schemes(args):
            "config": {"workload": "2D isothermal free growth, 781x781, h/W 1.2, W/d0* 16, "
                                   "Omega 0.43, eps4 0.014, k 0.1, alpha0 30 deg, S_{2,1} (full "
                                   "anti-trapping, App. B), FP32; S_{1,0} and S-bar_{2,1} beside",
-                      "nx": pr["nx"], "ny": pr["ny"], "h": pr["h"], "dt": pr["dt"]},
+                      "nx": pr["nx"], "ny": pr["ny"], "h": pr["h"], "dt": pr["dt"],
+                      "rows_per_segment": geo[0], "z_tile": geo[1]},
            "roofline": {"bound": "alu", "achieved": tf, "peak": PEAK_FP32_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(tf / PEAK_FP32_TFLOPS, 4),
-                        "traffic": None, "kernel": "step2d_kernel<float,isothermal,full-AT>",
-                        "kernel_ms": main_s["kernel_ms"]},
+                        "frac_of_nonpacked_fp32": round(tf / PEAK_FP32_NONPACKED_TFLOPS, 4),
+                        "traffic": None if ctr is None else ctr["hbm_bytes_per_launch"],
+                        "kernel": "step2d_kernel<float,isothermal,full-AT>",
+                        "kernel_ms": main_s["kernel_ms"],
+                        "counters_kernel_ns": None if ctr is None else ctr["avg_duration_ns"]},
            "cpu_baseline": cpu, "schemes": out_s}
     print(json.dumps(out))
 
@@ -541,6 +565,8 @@ def main():
     ap.add_argument("--no-serve-baselines", action="store_true",
                     help="serve: skip the one-at-a-time FP32/FP64 runs of the same trace")
     ap.add_argument("--hbm-budget-gib", type=float, default=2.0)
+    ap.add_argument("--schemes", default="S10,S21,Sbar21",
+                    help="schemes2d: schemes to run (S21 is the reported one)")
     ap.add_argument("--diffusion-sizes", default="8192x8192,1024x2048",
                     help="diffusion2d: lattices to run (8192x8192 is the reported one)")
     ap.add_argument("--no-cpu", action="store_true",
