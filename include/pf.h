@@ -192,19 +192,25 @@ int pf_device_fields(pf_solver *s, void **psi, void **U);
 int pf_frame_state(pf_solver *s, int64_t *shift, int32_t *pending);
 
 /* Launch geometry of the step kernels: rows per wave segment (2D and 3D,
- * 4..256) and z rows per workgroup (3D, 1..14 in FP32, 1..2 in FP64, within
- * the LDS of one workgroup; ignored in 2D).  Results do not
- * depend on it (only the work split changes); used by the tile autotuner. */
+ * 4..256; in 2D also -k for k = 1..64, asking for k waves per SIMD of the
+ * device: each 60-column strip then takes as many segments as give k * 4 *
+ * (compute units) waves in all, at most one per row, and the rows are split
+ * evenly between them) and z rows per workgroup (3D, 1..14 in FP32, 1..2 in
+ * FP64, within the LDS of one workgroup; ignored in 2D).  Results do not
+ * depend on it (only the work split changes); used by the tile autotuner.
+ * PF_ERR_ARG outside these ranges. */
 int pf_tune(pf_solver *s, int32_t rows_per_segment, int32_t z_tile);
 
 /* The launch geometry in use (the library's default for the lattice and
- * precision until pf_tune or pf_autotune changes it); z_tile is 1 in 2D.
+ * precision until pf_tune or pf_autotune changes it; the 2D default is a
+ * number of waves per SIMD, so rows_per_segment is negative); z_tile is 1
+ * in 2D.
  * Either pointer may be NULL.  PF_ERR_ARG for a NULL solver.  (Launch
  * geometry is not part of the paper's method: results never depend on it.) */
 int pf_geometry(pf_solver *s, int32_t *rows_per_segment, int32_t *z_tile);
 
-/* Tile autotuner: time each candidate launch geometry (2D: rows per segment
- * 4..64; 3D: rows per segment 8..64 times z rows per workgroup, within the
+/* Tile autotuner: time each candidate launch geometry (2D: 1..32 waves per
+ * SIMD, as pf_tune's -k; 3D: rows per segment 8..64 times z rows per workgroup, within the
  * LDS of one workgroup and at most 2 z rows in FP64) over steps_per_trial
  * steps (after 2 warm-up steps) with HIP events on the solver's stream, two
  * interleaved passes keeping each candidate's better time, and keep the
@@ -249,7 +255,9 @@ int pf_batch_use_graph(pf_batch *b, int32_t steps_per_graph);
 
 /* Batch autotuner: time the batched step for one segment length shared by
  * every member (4..32 rows) against the one in use (initially each member's
- * own, at least 8 rows) over steps_per_trial steps on scratch copies of all
+ * own segment length, at least 8 rows; for a member whose geometry asks for
+ * waves per SIMD, the longest segment that gives alone) over
+ * steps_per_trial steps on scratch copies of all
  * member workspaces, with the same two passes and 3% rule as pf_autotune,
  * then rebuild the batch with the choice (kept until the batch is destroyed;
  * it overrides the members' own pf_tune settings inside the batch only).  The

@@ -1,6 +1,7 @@
 // capi.hip -- the C ABI of include/pf.h: parameter validation, workspace
 // layout, state upload/download and the per-step launch sequence.
 #include <math.h>
+#include <cmath>
 #include <string.h>
 
 #include <algorithm>
@@ -33,19 +34,25 @@ int fail(int code, const std::string &msg) {
 
 // thin-interface constant a2 = 47/75 (Sec. 2.1): default lambda = D~ / a2
 constexpr double kA2 = 47.0 / 75.0;
-// Rows per wave segment in 2D: about 4.5 waves per SIMD on the 1024 SIMDs of
-// an MI355X when the lattice is small (short segments cost a 2-row psi
-// recompute each), up to 32 rows when there is work to spare; 6 rows when
-// 8-row segments would leave fewer than 2 waves per SIMD (sweeps on 781^2,
-// 1024x2048 and 8192x8192 lattices).  Batched members keep at least 8 rows:
-// the batch fills the chip by itself.
-constexpr int kMinSegBatch2D = 8;
-int default_seg2d(int nx, int ny) {
-  long long strips = (nx + 59) / 60;
-  if (strips * ((ny + 7) / 8) < 2048) return 6;
-  long long seg = strips * ny / 4608;
-  return (int)(seg < 8 ? 8 : (seg > 32 ? 32 : seg));
+// Default 2D geometry, -k: k waves per SIMD, so that the launch fills whole
+// rounds of the device (a fraction of a round leaves the SIMDs that hold one
+// wave more to finish alone).  Each segment recomputes about 1.5 rows of
+// work below it, so fewer, longer segments cost less, while more waves per
+// SIMD hide more latency.  With R = strips * ny / SIMDs rows per SIMD, k =
+// round(R^0.4) in FP32 and round(0.75 R^0.4) in FP64 (at most 3 waves of
+// the FP64 kernel fit a SIMD), within [1, 64]: fitted to sweeps of k on 256^2 ..
+// 8192^2 lattices, where it is the fastest k or within 2% of it (256^2: 1,
+// 1024x2048: 4, 4096^2: 9; against 4.5 rounds of fixed 8-row segments on
+// 1024x2048, 4% faster, and 14-64% on 256^2 .. 1024^2).
+int default_seg2d(int nx, int ny, int precision, int ncu) {
+  const double strips = (nx + 59) / 60;
+  const double R = strips * ny / (4.0 * std::max(1, ncu));
+  const double k = (precision == PF_F64 ? 0.75 : 1.0) * std::pow(R, 0.4);
+  return -std::min(64, std::max(1, (int)std::lround(k)));
 }
+// Batched members keep segments of at least 8 rows: the batch fills the chip
+// by itself.
+constexpr int kMinSegBatch2D = 8;
 // Default 3D geometry.  FP32: 14 z rows per workgroup (16 waves, the most
 // one workgroup holds: one workgroup per CU at the kernel's ~110 VGPRs, ring
 // waves costing 16/14 instead of 8/6 for two 6-row workgroups), with 32-row
@@ -129,7 +136,9 @@ Layout layout_of(const pf_params *p) {
   L.rot = o; o += align256((size_t)(p->n_grains > 0 ? p->n_grains : 1) * 9 * es);
   for (int i = 0; i < 3; ++i) { L.frame[i] = o; o += 256; }
   // per-block partials: enough for the finest segmentation the step accepts
-  int nb = std::max(max_step_blocks(p, 4, 1), reduce_blocks(p->nx, p->ny, p->dim == 3 ? p->nz : 1));
+  // (2D: one row per segment; 3D: 4 rows)
+  int nb = std::max(max_step_blocks(p, p->dim == 2 ? 1 : 4, 1),
+                    reduce_blocks(p->nx, p->ny, p->dim == 3 ? p->nz : 1));
   L.partials = o; o += align256((size_t)(nb + 64) * tip_acc_bytes());
   L.counter = o; o += 256;
   L.result = o; o += 256;
@@ -224,12 +233,21 @@ struct pf_solver {
   int cur;    // current field buffers
   int fcur;   // current frame record (0..2, advances with the frame on)
   long long step;
-  int seg, ztile;
+  int seg, ztile;  // launch geometry (2D seg < 0: -(waves per SIMD))
+  int ncu;         // compute units of the device the solver was created on
   bool have_prev;
   double prev_t, prev_y;
 };
 
 namespace {
+
+// Rows per segment of the solver's 2D geometry (the longest segment when it
+// asks for waves per SIMD).
+int rows2d(const pf_solver *s) {
+  if (s->seg > 0) return s->seg;
+  const Geom2D g = geom2d(s->p.nx, s->p.ny, s->seg, s->ncu);
+  return g.segbase + (g.segrem ? 1 : 0);
+}
 
 template <typename T>
 T *field(pf_solver *s, size_t off) {
@@ -335,13 +353,16 @@ template <typename T>
 Geom2D fill2d(pf_solver *s, Step2DArgs<T> &a, int min_seg = 1, int seg_fixed = 0) {
   const pf_params &p = s->p;
   memset(&a, 0, sizeof(a));
-  Geom2D g = geom2d(p.nx, p.ny, seg_fixed > 0 ? seg_fixed : std::max(s->seg, min_seg));
+  Geom2D g = seg_fixed > 0   ? geom2d(p.nx, p.ny, seg_fixed)
+             : min_seg <= 1 ? geom2d(p.nx, p.ny, s->seg, s->ncu)
+                            : geom2d(p.nx, p.ny, std::max(rows2d(s), min_seg));
   a.grain = p.n_grains > 1 ? grain_buf(s, s->cur) : nullptr;
   a.grain_out = p.dynamic_grains ? grain_buf(s, 1 - s->cur) : nullptr;
   a.rot = field<T>(s, s->L.rot);
   a.r00 = (T)s->rot[0]; a.r01 = (T)s->rot[1]; a.r10 = (T)s->rot[3]; a.r11 = (T)s->rot[4];
   a.nx = p.nx; a.ny = p.ny; a.bcx = p.bc[0]; a.bcy = p.bc[1];
-  a.wout = g.wout; a.nstrips = g.nstrips; a.nsegs = g.nsegs; a.seg = g.seg;
+  a.wout = g.wout; a.nstrips = g.nstrips; a.nsegs = g.nsegs;
+  a.segbase = g.segbase; a.segrem = g.segrem;
   a.c = coef_of<T>(s);
   a.hd = p.h; a.y0 = p.y0; a.Vp = p.Vp; a.dtd = s->dt;
   a.frame = p.frame; a.shift_row = p.shift_row;
@@ -652,8 +673,15 @@ int autotune_impl(pf_solver *s, int steps) {
     if (seg != s->seg || zt != s->ztile) cand.push_back({seg, zt});
   };
   if (s->p.dim == 2) {
-    for (int seg : {4, 6, 8, 10, 12, 16, 24, 32, 48, 64})
-      if (seg <= std::max(4, s->p.ny)) add(seg, s->ztile);
+    // waves per SIMD; counts that give the same segments as one already
+    // listed are skipped
+    std::vector<int> nsegs = {geom2d(s->p.nx, s->p.ny, s->seg, s->ncu).nsegs};
+    for (int k : {1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32}) {
+      const int n = geom2d(s->p.nx, s->p.ny, -k, s->ncu).nsegs;
+      if (std::find(nsegs.begin(), nsegs.end(), n) != nsegs.end()) continue;
+      nsegs.push_back(n);
+      add(-k, s->ztile);
+    }
   } else {
     const int zmax = s->p.precision == PF_F64 ? 2 : 14;
     for (int zt : {1, 2, 4, 5, 6, 8, 10, 12, 14})
@@ -697,7 +725,7 @@ int batch_autotune_impl(pf_batch *b, int steps) {
   tb.gexec = nullptr;
   for (int i = 0; i < made; ++i) tb.s.push_back(&clones[i]);
   tb.expect.assign(made, -1);
-  tb.seg.assign(made, -1);
+  tb.seg.assign(made, 0);
   // candidate 0: the segment length in use (0 = each member's own)
   std::vector<int> cand = {b->seg_fixed};
   for (int seg : {4, 6, 8, 12, 16, 24, 32})
@@ -760,7 +788,7 @@ int pf_batch_create(pf_solver *const *solvers, int32_t n, pf_batch **out) {
   b->table = nullptr;
   b->map = nullptr;
   b->expect.assign(n, -1);
-  b->seg.assign(n, -1);
+  b->seg.assign(n, 0);
   b->graph_steps = 0;
   b->seg_fixed = 0;
   b->graph = nullptr;
@@ -887,12 +915,6 @@ int pf_create(const pf_params *p, const pf_init *init, void *workspace, size_t w
   s->cur = 0;
   s->fcur = 0;
   s->step = 0;
-  if (p->dim == 2) {
-    s->seg = default_seg2d(p->nx, p->ny);
-    s->ztile = 1;
-  } else {
-    std::tie(s->seg, s->ztile) = default_geom3d(p);
-  }
   s->have_prev = false;
   if (workspace) {
     if (workspace_bytes < L.total || (reinterpret_cast<uintptr_t>(workspace) & 255u)) {
@@ -912,7 +934,23 @@ int pf_create(const pf_params *p, const pf_init *init, void *workspace, size_t w
     s->ws_bytes = L.total;
     s->own = true;
   }
-  int r2 = p->precision == PF_F64 ? upload<double>(s, init) : upload<float>(s, init);
+  int r2 = PF_OK;
+  {
+    int dev = 0;
+    s->ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&s->ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        s->ncu < 1)
+      r2 = fail(PF_ERR_DEVICE, "cannot read the device's compute unit count");
+  }
+  if (p->dim == 2) {
+    s->seg = default_seg2d(p->nx, p->ny, p->precision, s->ncu);
+    s->ztile = 1;
+  } else {
+    std::tie(s->seg, s->ztile) = default_geom3d(p);
+  }
+  if (r2 == PF_OK)
+    r2 = p->precision == PF_F64 ? upload<double>(s, init) : upload<float>(s, init);
   if (r2 == PF_OK && p->n_grains > 1) {
     std::vector<int8_t> g(n, 0);
     if (init->grain) memcpy(g.data(), init->grain, n);
@@ -1039,8 +1077,13 @@ int pf_frame_state(pf_solver *s, int64_t *shift, int32_t *pending) {
 
 int pf_tune(pf_solver *s, int32_t rows_per_segment, int32_t z_tile) {
   if (!s) return fail(PF_ERR_ARG, "solver is NULL");
+  if (s->p.dim == 2 && rows_per_segment >= -64 && rows_per_segment <= -1) {
+    s->seg = rows_per_segment;  // -k: k waves per SIMD
+    return PF_OK;
+  }
   if (rows_per_segment < 4 || rows_per_segment > 256)
-    return fail(PF_ERR_ARG, "rows_per_segment must lie in [4, 256]");
+    return fail(PF_ERR_ARG, s->p.dim == 2 ? "rows_per_segment must lie in [4, 256] or [-64, -1]"
+                                          : "rows_per_segment must lie in [4, 256]");
   if (s->p.dim == 3 && (z_tile < 1 || z_tile > 14))
     return fail(PF_ERR_ARG, "z_tile must lie in [1, 14]");
   if (s->p.dim == 3 && s->p.precision == PF_F64 && z_tile > 2)

@@ -72,7 +72,7 @@ struct Step2DArgs {
   const T *rot;          // multi-grain only: 4 per grain (r00, r01, r10, r11)
   T r00, r01, r10, r11;  // single grain
   int nx, ny, bcx, bcy;
-  int wout, nstrips, nsegs, seg;
+  int wout, nstrips, nsegs, segbase, segrem;
   Coef<T> c;
   double hd, y0, Vp, dtd;
   long long step;
@@ -121,12 +121,14 @@ struct ReduceArgs {
   Reduce red;
 };
 
-// Launch geometry of the 2D step: wave64 strips of up to 60 output columns,
-// segments of `seg` rows.
+// Launch geometry of the 2D step: wave64 strips of up to 60 output columns
+// and, per strip, ceil(ny / seg) segments for seg > 0, or for seg = -k as
+// many as give k waves per SIMD over ncu compute units (at most ny); the rows
+// are split evenly (segbase rows each, one more for the first segrem).
 struct Geom2D {
-  int wout, nstrips, nsegs, seg, blocks;
+  int wout, nstrips, nsegs, seg, segbase, segrem, blocks;
 };
-Geom2D geom2d(int nx, int ny, int seg);
+Geom2D geom2d(int nx, int ny, int seg, int ncu = 0);
 
 struct Geom3D {
   int wout, nstrips, ztile, nzt, nsegs, seg, blocks, threads;

@@ -122,8 +122,9 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
     const int x = strip * a.wout - 2 + lane;
     const int gx = ghost(x, nx, a.bcx);
     const bool out_lane = lane >= 2 && lane < 2 + a.wout && x < nx;
-    const int y0 = segi * a.seg;
-    const int ye = min(y0 + a.seg, ny);
+    // rows split evenly: the first segrem segments take one row more
+    const int y0 = segi * a.segbase + min(segi, a.segrem);
+    const int ye = y0 + a.segbase + (segi < a.segrem ? 1 : 0);
     const int pend = a.frame ? a.frame_in->pending : 0;
     const long long shift = a.frame ? a.frame_in->base + pend : 0;
     T off = T(0);
@@ -507,12 +508,20 @@ __global__ void batch2d_advance(BatchSolve2D<T> *table, int n, int steps, int fr
 
 }  // namespace
 
-Geom2D geom2d(int nx, int ny, int seg) {
+Geom2D geom2d(int nx, int ny, int seg, int ncu) {
   Geom2D g;
   g.nstrips = (nx + 59) / 60;
   g.wout = (nx + g.nstrips - 1) / g.nstrips;
-  g.seg = seg < 1 ? 1 : seg;
-  g.nsegs = (ny + g.seg - 1) / g.seg;
+  g.seg = seg == 0 ? 1 : seg;
+  if (g.seg > 0) {
+    g.nsegs = (ny + g.seg - 1) / g.seg;
+  } else {
+    // -k: k waves per SIMD, i.e. k * 4 * ncu waves in all (4 SIMDs per CU)
+    const long long want = (long long)(-g.seg) * 4 * (ncu > 0 ? ncu : 1) / g.nstrips;
+    g.nsegs = (int)std::max(1LL, std::min((long long)ny, want));
+  }
+  g.segbase = ny / g.nsegs;
+  g.segrem = ny % g.nsegs;
   int waves = g.nstrips * g.nsegs;
   g.blocks = (waves + 3) / 4;
   return g;

@@ -228,10 +228,13 @@ class Solver:
         return a.value, b.value
 
     def tune(self, rows_per_segment: int, z_tile: int = 1):
+        """Launch geometry: rows per wave segment (4..256), or in 2D -k for k
+        waves per SIMD (1..64); z rows per workgroup in 3D."""
         _check(load().pf_tune(self.handle, int(rows_per_segment), int(z_tile)))
 
     def geometry(self):
-        """(rows_per_segment, z_tile) of the step launches in use."""
+        """(rows_per_segment, z_tile) of the step launches in use (negative
+        rows_per_segment: -(waves per SIMD), the 2D default)."""
         seg, zt = C.c_int32(), C.c_int32()
         _check(load().pf_geometry(self.handle, C.byref(seg), C.byref(zt)))
         return seg.value, zt.value

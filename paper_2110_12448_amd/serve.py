@@ -70,15 +70,22 @@ def _batchable(prob: dict) -> bool:
     return prob["dim"] == 2 and not prob.get("antitrapping", 0) and not prob.get("two_point", 0)
 
 
-def estimated_waves(prob: dict) -> int:
+def estimated_waves(prob: dict, batched: bool = False, cus: int = 256) -> int:
     """Waves one step launch of this solve occupies at the library's default
-    geometry (60 output columns per wave; 2D segments of about 8 rows; 3D
-    workgroups of 14 z rows in 16 waves, on segments of 32 rows when that
-    gives 400 workgroups, else 16 rows when that gives 200, else 8): the
-    measure of how much of the chip a solve fills on its own."""
+    FP32 geometry on a device of `cus` compute units: the measure of how much
+    of the chip a solve fills.  60 output columns per wave; in 2D k =
+    round(R^0.4) waves per SIMD with R = strips * ny / SIMDs, at most one
+    segment per row, and inside a batch segments of that length but at least
+    8 rows; 3D workgroups of 14 z rows in 16 waves, on segments of 32 rows
+    when that gives 400 workgroups, else 16 rows when that gives 200, else 8."""
     strips = -(-prob["nx"] // 60)
     if prob["dim"] == 2:
-        return strips * -(-prob["ny"] // 8)
+        ny, simds = prob["ny"], 4 * cus
+        k = max(1, int(np.floor((strips * ny / simds) ** 0.4 + 0.5)))
+        nsegs = max(1, min(ny, k * simds // strips))
+        if batched:
+            nsegs = -(-ny // max(8, -(-ny // nsegs)))
+        return strips * nsegs
     zt = min(14, prob["nz"])
     tiles = -(-prob["nz"] // zt)
     blocks = {s: strips * -(-prob["ny"] // s) * tiles for s in (32, 16, 8)}
@@ -193,7 +200,8 @@ class Server:
                         geo[cls] = s.autotune(self.autotune_steps)
                     else:
                         s.tune(*geo[cls])
-                active.append(_Active(r, s, now(), 0, need, estimated_waves(r.problem)))
+                active.append(_Active(r, s, now(), 0, need, estimated_waves(
+                    r.problem, batched=self.batching and _batchable(r.problem))))
                 used += need
                 waves += active[-1].waves
             if not active:

@@ -52,7 +52,7 @@ def test_autotune_keeps_state_and_results(case):
     assert s.geometry() == (seg, zt)
     assert _same(_state(s), pre)
     if dim == 2:
-        assert 4 <= seg <= 64 and zt == 1
+        assert -64 <= seg <= -1 and zt == 1      # waves per SIMD
     else:
         assert 8 <= seg <= 64 and 1 <= zt <= (2 if prec == 1 else 14)
     s.tune(seg, zt)                      # the choice is accepted as a manual setting

@@ -216,11 +216,13 @@ def test_nonfinite_detected():
 @pytest.mark.parametrize("kw", [{}, wl.SCHEMES_2D["S21"], wl.SCHEMES_2D["S10"]])
 def test_segment_length_does_not_change_results(prec, kw):
     """Rows per wave segment (pf_tune) only move the recomputed halo rows: the
-    results are bitwise the same for every segment length, ragged or not."""
+    results are bitwise the same for every segment length, split evenly or
+    not, down to one row per segment (-k: k waves per SIMD, which on this
+    lattice asks for more segments than rows)."""
     pf = _pf()
     pr = wl.config_small_2d(30.0, n=150, frame=1, shift_row=20, **kw)
     out = []
-    for seg in (4, 6, 8, 13, 32):
+    for seg in (4, 6, 8, 13, 32, -1, -3):
         s = pf.Solver(pr, precision=prec)
         s.tune(seg, 1)
         s.step(40)
@@ -230,6 +232,36 @@ def test_segment_length_does_not_change_results(prec, kw):
     for psi, U, shift in out[1:]:
         assert np.array_equal(psi, out[0][0]) and np.array_equal(U, out[0][1])
         assert shift == out[0][2]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_waves_per_simd_geometry(prec):
+    """The 2D default asks for k waves per SIMD (negative rows_per_segment);
+    on 250^2 (5 strips) one wave per SIMD gives 1- and 2-row segments, two
+    give one row each, and 20 and 64 clamp to one segment per row: all give
+    the bits of 8-row segments."""
+    pf = _pf()
+    pr = wl.config_small_2d(0.0, n=250, frame=1, shift_row=30)
+    s = pf.Solver(pr, precision=prec)
+    assert s.geometry()[0] < 0
+    s.close()
+    out = []
+    for seg in (8, -1, -2, -20, -64):
+        s = pf.Solver(pr, precision=prec)
+        s.tune(seg, 1)
+        assert s.geometry() == (seg, 1)
+        s.step(30)
+        phi, U, psi, _ = s.read_fields()
+        out.append((psi, U, s.tip_state()["y_lab"]))
+        s.close()
+    for psi, U, y in out[1:]:
+        assert np.array_equal(psi, out[0][0]) and np.array_equal(U, out[0][1]) and y == out[0][2]
+    s = pf.Solver(pr, precision=prec)
+    for seg in (-65, 0, 3, 257):
+        with pytest.raises(pf.PFError) as e:
+            s.tune(seg, 1)
+        assert e.value.code == pf.PF_ERR_ARG, seg
+    s.close()
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -257,7 +289,7 @@ def test_tune_limits_3d():
     pf = _pf()
     pr = wl.problem(3, (16, 16, 16))
     s = pf.Solver(pr, precision=pf.PF_F64)
-    for seg, zt in ((8, 9), (8, 3), (300, 2)):
+    for seg, zt in ((8, 9), (8, 3), (300, 2), (-2, 2)):   # waves per SIMD: 2D only
         with pytest.raises(pf.PFError) as e:
             s.tune(seg, zt)
         assert e.value.code == pf.PF_ERR_ARG, (seg, zt)

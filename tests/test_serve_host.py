@@ -22,15 +22,19 @@ def test_trace_is_seeded_and_mixed():
             assert r.problem["nx"] in (128, 160, 192)
 
 
-@pytest.mark.parametrize("shape,want", [
-    ((256, 256), 5 * 32),                        # 2D: 60-column strips x 8-row segments
-    ((1024, 1024), 18 * 128),
-    ((128, 128, 128), 3 * 8 * 10 * 16),          # 3D, few workgroups: 16-row segments
-    ((256, 256, 256), 5 * 8 * 19 * 16),          # 3D, many: 32-row segments, 14 z rows
+@pytest.mark.parametrize("shape,batched,want", [
+    ((256, 256), False, 5 * 204),                # 2D alone: 1 wave per SIMD, 1-2 row segments
+    ((1024, 1024), False, 18 * 170),             # 3 waves per SIMD (18^0.4 = 3.2)
+    ((1024, 2048), False, 18 * 227),             # 4 (36^0.4 = 4.2)
+    ((256, 256), True, 5 * 32),                  # batched: 60-column strips x 8-row segments
+    ((1024, 1024), True, 18 * 128),
+    ((2048, 2048), True, 35 * 137),              # longer alone (146 segments): 15 rows
+    ((128, 128, 128), False, 3 * 8 * 10 * 16),   # 3D, few workgroups: 16-row segments
+    ((256, 256, 256), False, 5 * 8 * 19 * 16),   # 3D, many: 32-row segments, 14 z rows
 ])
-def test_estimated_waves(shape, want):
+def test_estimated_waves(shape, batched, want):
     pr = wl.problem(len(shape), shape, noise=0.0)
-    assert serve.estimated_waves(pr) == want
+    assert serve.estimated_waves(pr, batched=batched) == want
 
 
 def test_policy_switches_validated():
