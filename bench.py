@@ -297,6 +297,7 @@ def _copy_GBs(nbytes=1 << 30, reps=10):
 
 
 # counter summary of the diffusion-only kernel on 8192^2 (HBM regime)
+DIFFUSION_ROWS_PER_SEGMENT = 16
 DIFFUSION_COUNTERS = dict(
     sources=["paper_2110_12448_amd/csrc/step2d.hip", "paper_2110_12448_amd/csrc/pf_device.hpp"],
     counters="profiles/step2d_diffusion_8192x8192_counters.json")
@@ -324,6 +325,10 @@ def bench_diffusion(args):
         cells = pr["nx"] * pr["ny"]
         s = pfiso.Solver(pr, precision=pfiso.PF_F32)
         st = s.stream
+        # HBM-bound: many short segments keep more loads in flight than the
+        # full step's default (waves per SIMD sized for VALU issue); 16-row
+        # segments were the fastest of 16, 32, 64 rows and 16..64 waves per SIMD
+        s.tune(DIFFUSION_ROWS_PER_SEGMENT, 1)
         if label == "8192x8192":
             geo = s.geometry()
         print("bench: diffusion2d %s FP32, warmup %d, steps %d, geometry %s" % (
