@@ -103,8 +103,39 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return x * q + (x < r ? x : r) + b / X;
 }
 
+// Store v at column x of the row starting at `row` (nx elements) from the
+// lanes with ok set, without a branch: a raw buffer store whose record is the
+// row, the other lanes given an offset beyond it, which the hardware drops.
+// Straight-line stores keep a whole row of the pipeline in one basic block.
+template <typename T>
+__device__ __forceinline__ void store_row(T *row, int nx, int x, bool ok, T v) {
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(row, 0, nx * (int)sizeof(T), 0x00020000);
+  const int off = ok ? x * (int)sizeof(T) : 0x40000000;
+  if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rs, off, 0, 0);
+  } else {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, off, 0, 0);
+  }
+}
+
+// Waves per SIMD the register budget must leave room for.  The steady-state
+// row group is one basic block, so the scheduler overlaps rows freely: FP32
+// variants settle at 85-131 VGPRs (3-5 waves per SIMD) and run fastest
+// unconstrained; the FP64 approximated-current single-grain variants would
+// take 200+ VGPRs (2 waves) and run 6-18% faster held to 3 waves (168 VGPRs,
+// no spills).  The other FP64 variants would spill there and stay
+// unconstrained.
+template <typename T, bool kMulti, int kAT>
+constexpr int kMinWaves2D =
+    sizeof(T) == 8 && !kMulti &&
+            (kAT == kAtApproxShells || kAT == kAtApproxTwoPoint || kAT == kAtDiffusionOnly)
+        ? 3
+        : 1;
+
 // One logical workgroup `lb` (4 waves) of the step of one solve `a`.
-template <typename T, bool kFrozen, bool kReduce, bool kMulti, int kAT>
+template <typename T, bool kFrozen, bool kReduce, bool kMulti, int kAT, bool kRowTail = true>
 __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb) {
   constexpr bool kTwoPoint = kAT == kAtFullTwoPoint || kAT == kAtApproxTwoPoint;
   constexpr bool kDiff = kAT == kAtDiffusionOnly;
@@ -138,6 +169,15 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
       int j = ghost_near(r, ny, a.bcy);
       if (pend) j = min(j + 1, ny - 1);
       return (size_t)j * (size_t)nx + (size_t)gx;
+    };
+    // the same for the steady state, whose rows (y0 + 5 .. ye + 1) can only
+    // cross the top boundary, in plain arithmetic: no branch splits the row
+    const int top_per = a.bcy == PF_BC_PERIODIC ? ny : 0;
+    const int top_mir = a.bcy == PF_BC_PERIODIC ? 0 : 1;
+    auto prow_top = [&](int r) -> size_t {
+      const int over = max(r - (ny - 1), 0);  // 0, 1 or 2 rows past the top
+      const int j = r - top_per * min(over, 1) - top_mir * max(2 * over - 1, 0);
+      return (size_t)min(j + pend, ny - 1) * (size_t)nx + (size_t)gx;
     };
     auto rot_of = [&](int g) -> Rot2<T> {
       if (kMulti) {
@@ -177,6 +217,14 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
     // y0-2), 1 adds the y face flux, 2 the psi rate of row y0-1, 3 the first
     // stored psi row and the divergence carries of the pair (y0-1, y0), 4 is
     // the steady state with every stage active.
+    // moving-frame decision: an interface cell of row m whose
+    // phi = 0 crossing lies at or above the shift row.  Rows at or above it
+    // qualify outright and rows below the one under it cannot (the crossing
+    // lies within one row), so the loop votes with plain masks; the FP64
+    // crossing height of the row under the shift row is taken once, below.
+    auto frame_vote = [&](int m, T f0, T f1) -> bool {
+      return out_lane & (m >= a.shift_row) & (m <= ny - 2) & (f0 >= T(0)) & (f1 < T(0));
+    };
     auto iter = [&](auto phase, int r) {
       constexpr int P = decltype(phase)::value;
       if constexpr (kAT == kAtFullShells) {
@@ -196,8 +244,10 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
       pN = lp0; uN = lu0; gN = lg0;
       lp0 = lp1; lu0 = lu1; lg0 = lg1;
       lp1 = lp2; lu1 = lu2; lg1 = lg2;
-      if (r + 3 <= ye + 1) {
-        size_t on = prow(r + 3);
+      if (P >= 5 || r + 3 <= ye + 1) {
+        // steady state: the last rows reload row ye + 1 (never consumed)
+        // instead of branching around the load
+        size_t on = P >= 5 ? prow_top(min(r + 3, ye + 1)) : prow(r + 3);
         lp2 = a.psi_in[on];
         lu2 = a.U_in[on];
         if (kMulti) lg2 = a.grain[on];
@@ -249,10 +299,8 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
         const int m = r - 1;
         grain_next(m);
         if (P >= 3 && m < ye) {
-          if (out_lane) a.psi_out[(size_t)m * (size_t)nx + (size_t)x] = pC;
-          if (kReduce && out_lane && m <= ny - 2 && m + 1 >= a.shift_row && fC >= T(0) &&
-              fN < T(0))
-            over |= crossing_reaches(fC, fN, m, a.shift_row, ythr, a.hd);
+          store_row(a.psi_out + (size_t)m * (size_t)nx, nx, x, out_lane, pC);
+          if (kReduce) over = over | frame_vote(m, fC, fN);
         }
       } else if constexpr (P >= 2) {
         // ---------------- psi rate at row m (window rows S, C, N = m-1, m, m+1)
@@ -273,7 +321,7 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
         T Nn = (FxE - FxW + FyN - FyS - ac2 * s10) * c.cStd;
         T F1 = T(1), F2 = uC;
         if (kFrozen) {
-          T zeta = (T)ghost_near(m, ny, a.bcy) * c.h + off;
+          T zeta = (T)(P >= 5 ? m : ghost_near(m, ny, a.bcy)) * c.h + off;
           F1 = T(1) - c.omk * zeta * c.inv_lT;
           F2 = uC + zeta * c.inv_lT;
         }
@@ -282,22 +330,20 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
         T rhs = ac2 * (L - sq2 * ph * G) + Nn + sq2 * (ph - c.lambda * omp * F2);
         T rate = rhs * M::rcp(F1 * ac2);
         T aA = (T(1) + c.omk * uC) * omp * rate * T(0.5);
-        if (a.bcx == PF_BC_NOFLUX) {  // mirrored columns copy their image
+        if (P == 6 || (P < 5 && a.bcx == PF_BC_NOFLUX)) {  // mirrored columns copy their image
           T fr = from_right(aA), fl = from_left(aA);
           aA = (x == -1) ? fr : ((x == nx) ? fl : aA);
         }
         aAC = aA;
         // mirrored rows copy their image (rows 0 and ny, never met inside the
         // unrolled steady state: phase 5)
-        if (P != 5 && a.bcy == PF_BC_NOFLUX) {
+        if (P < 5 && a.bcy == PF_BC_NOFLUX) {
           if (m == 0) aAS = aAC;
           if (m == ny) aAC = aAS;
         }
-        if (P >= 3 && m < ye) {
-          if (out_lane) a.psi_out[(size_t)m * (size_t)nx + (size_t)x] = pC + c.dt * rate;
-          if (kReduce && out_lane && m <= ny - 2 && m + 1 >= a.shift_row && fC >= T(0) &&
-              fN < T(0))  // interface cell: frame decision on its crossing height
-            over |= crossing_reaches(fC, fN, m, a.shift_row, ythr, a.hd);
+        if (P >= 5 || (P >= 3 && m < ye)) {
+          store_row(a.psi_out + (size_t)m * (size_t)nx, nx, x, out_lane, pC + c.dt * rate);
+          if (kReduce) over = over | frame_vote(m, fC, fN);
         }
       }
       FyS = FyN;
@@ -334,7 +380,7 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
         if constexpr (P >= 4) {
           T div = c.cT * (fE - from_left(fE) + fN - cN);
           T rU = (div + sq2 * aAS) * M::rcp(T(1) + c.k - c.omk * fS);
-          if (out_lane) a.U_out[(size_t)q * (size_t)nx + (size_t)x] = uS + c.dt * rU;
+          store_row(a.U_out + (size_t)q * (size_t)nx, nx, x, out_lane, uS + c.dt * rU);
         }
         cN = fN;
       } else if constexpr (P >= 3) {
@@ -418,7 +464,7 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
                   c.cD2 * (d1 + d2 - from_left(c1) - from_right(c2));
           // the held psi has no anti-trapping current and no source
           T rU = (kDiff ? div : div + sq2 * aAS) * M::rcp(T(1) + c.k - c.omk * fS);
-          if (out_lane) a.U_out[(size_t)q * (size_t)nx + (size_t)x] = uS + c.dt * rU;
+          store_row(a.U_out + (size_t)q * (size_t)nx, nx, x, out_lane, uS + c.dt * rU);
         }
         cN = fN; c1 = d1; c2 = d2; cPD = PD; cPA = PA;
       }
@@ -429,6 +475,7 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
     using I3 = std::integral_constant<int, 3>;
     using I4 = std::integral_constant<int, 4>;
     using I5 = std::integral_constant<int, 5>;  // phase 4 on rows 1..ny-1
+    using I6 = std::integral_constant<int, 6>;  // phase 5, mirrored x columns
     iter(I0{}, y0 - 2);
     iter(I1{}, y0 - 1);
     iter(I2{}, y0);
@@ -437,18 +484,50 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
     // period (3 for the row window, the grains and the loads in flight, 2 for
     // alpha_A, 1 for the carries), so the rotation costs no register moves.
     // Its psi rows m = r - 1 run from y0 + 1 to at most ye - 1, so none is
-    // row 0 or ny (the last row of a segment goes to the loop below).
+    // row 0 or ny.
+    // The rows left over (fewer than 6) run one at a time, still straight-line
+    // (the window then rotates by register moves); only the last iteration,
+    // whose psi row ye belongs to the next segment, takes the checked phase 4.
+    // Without kRowTail (batched launches: long segments, and waves of many
+    // solves at different points of the code) they take phase 4, which keeps
+    // the code smaller.
     int r = y0 + 2;
-    for (; r + 5 <= ye; r += 6) {
-      iter(I5{}, r);
-      iter(I5{}, r + 1);
-      iter(I5{}, r + 2);
-      iter(I5{}, r + 3);
-      iter(I5{}, r + 4);
-      iter(I5{}, r + 5);
+    if (a.bcx == PF_BC_NOFLUX) {  // phase 6: phase 5 with mirrored columns
+      for (; r + 5 <= ye; r += 6) {
+        iter(I6{}, r);
+        iter(I6{}, r + 1);
+        iter(I6{}, r + 2);
+        iter(I6{}, r + 3);
+        iter(I6{}, r + 4);
+        iter(I6{}, r + 5);
+      }
+      if constexpr (kRowTail)
+        for (; r <= ye; ++r) iter(I6{}, r);
+    } else {
+      for (; r + 5 <= ye; r += 6) {
+        iter(I5{}, r);
+        iter(I5{}, r + 1);
+        iter(I5{}, r + 2);
+        iter(I5{}, r + 3);
+        iter(I5{}, r + 4);
+        iter(I5{}, r + 5);
+      }
+      if constexpr (kRowTail)
+        for (; r <= ye; ++r) iter(I5{}, r);
     }
     for (; r <= ye + 1; ++r) iter(I4{}, r);
-    if (kReduce) over_any = __any(over);
+    if (kReduce) {
+      // the row under the shift row: its crossing height in FP64, on the phi
+      // the pipeline computed from the same loads
+      const int ms = a.shift_row - 1;
+      if (ms >= y0 && ms < ye && ms <= ny - 2) {
+        const T f0 = M::tanh_(a.psi_in[prow(ms)] * isq2);
+        const T f1 = M::tanh_(a.psi_in[prow(ms + 1)] * isq2);
+        if (out_lane && f0 >= T(0) && f1 < T(0))
+          over |= crossing_reaches(f0, f1, ms, a.shift_row, ythr, a.hd);
+      }
+      over_any = __any(over);
+    }
   }
 
   if (kReduce) {
@@ -466,7 +545,8 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
 }
 
 template <typename T, bool kFrozen, bool kReduce, bool kMulti, int kAT>
-__global__ __launch_bounds__(256) void step2d_kernel(Step2DArgs<T> a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves2D<T, kMulti, kAT>)))
+void step2d_kernel(Step2DArgs<T> a) {
   step2d_body<T, kFrozen, kReduce, kMulti, kAT>(a, xcd_remap((int)blockIdx.x, (int)gridDim.x));
 }
 
@@ -474,7 +554,9 @@ __global__ __launch_bounds__(256) void step2d_kernel(Step2DArgs<T> a) {
 // solve map[b].x.  Launch k of an epoch steps every solve from its level
 // n0 + k: buffers and frame records are picked from the epoch's parities.
 template <typename T, bool kFrozen, bool kReduce, bool kMulti>
-__global__ __launch_bounds__(256) void batch2d_kernel(const BatchSolve2D<T> *table,
+__global__ __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(kMinWaves2D<T, kMulti, kAtApproxShells>)))
+void batch2d_kernel(const BatchSolve2D<T> *table,
                                                       const int2 *map, int k) {
   const int2 bm = map[blockIdx.x];
   const BatchSolve2D<T> &e = table[bm.x];
@@ -492,7 +574,7 @@ __global__ __launch_bounds__(256) void batch2d_kernel(const BatchSolve2D<T> *tab
     a.frame_out = e.frames[(f + 1) % 3];
     a.frame_clear = e.frames[(f + 2) % 3];
   }
-  step2d_body<T, kFrozen, kReduce, kMulti, kAtApproxShells>(a, bm.y);
+  step2d_body<T, kFrozen, kReduce, kMulti, kAtApproxShells, false>(a, bm.y);
 }
 
 // Advance the epoch origin of every solve by `steps` (end of a captured graph).
