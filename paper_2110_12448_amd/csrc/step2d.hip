@@ -103,23 +103,6 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return x * q + (x < r ? x : r) + b / X;
 }
 
-// Store v at column x of the row starting at `row` (nx elements) from the
-// lanes with ok set, without a branch: a raw buffer store whose record is the
-// row, the other lanes given an offset beyond it, which the hardware drops.
-// Straight-line stores keep a whole row of the pipeline in one basic block.
-template <typename T>
-__device__ __forceinline__ void store_row(T *row, int nx, int x, bool ok, T v) {
-  const __amdgpu_buffer_rsrc_t rs =
-      __builtin_amdgcn_make_buffer_rsrc(row, 0, nx * (int)sizeof(T), 0x00020000);
-  const int off = ok ? x * (int)sizeof(T) : 0x40000000;
-  if constexpr (sizeof(T) == 4) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rs, off, 0, 0);
-  } else {
-    typedef unsigned u2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, off, 0, 0);
-  }
-}
-
 // Waves per SIMD the register budget must leave room for.  The steady-state
 // row group is one basic block, so the scheduler overlaps rows freely: FP32
 // variants settle at 85-131 VGPRs (3-5 waves per SIMD) and run fastest

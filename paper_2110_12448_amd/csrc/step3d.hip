@@ -230,9 +230,8 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
     const int par = qf & 1;
     const T below = XL[((par * 2 + 0) * NW + (w - 1)) * 64 + lane];
     const T above = XL[((par * 2 + 1) * NW + (w + 1)) * 64 + lane];
-    if (out_lane)
-      a.U_out[pz + (size_t)qf * nx - (size_t)gx + (size_t)x] =
-          waitU + c.dt * waitDen * (waitBase - below - above);
+    store_row(a.U_out + (pz - (size_t)gx) + (size_t)qf * nx, nx, x, out_lane,
+               waitU + c.dt * waitDen * (waitBase - below - above));
   };
 
   auto iter = [&](auto phase, int r) {
@@ -241,8 +240,10 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
     pS = pC; pC = pN; uS = uC; uC = uN; fS = fC; fC = fN; gS = gC; gC = gN;
     pN = nxt_p; uN = nxt_u; gN = nxt_g;
     const T hN = nxt_h;
-    if (r + 1 <= ye + 1) {
-      size_t ro = rowoff(r + 1);
+    {
+      // the last iteration reloads row ye + 1 (never consumed) rather than
+      // branching around the loads
+      size_t ro = rowoff(min(r + 1, ye + 1));
       nxt_p = a.psi_in[pz + ro];
       nxt_u = a.U_in[pz + ro];
       if (ring) nxt_h = a.psi_in[pzh + ro];
@@ -402,10 +403,13 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
             a.grain_out[pz + (size_t)m * nx - (size_t)gx + (size_t)x] = (int8_t)gn;
         }
       }
-      if (P >= 3 && m < ye && out_wave && out_lane) {
-        a.psi_out[pz + (size_t)m * nx - (size_t)gx + (size_t)x] = pC + c.dt * rate;
-        if (kReduce && m <= ny - 2 && m + 1 >= a.shift_row && fC >= T(0) && fN < T(0))
-          over |= crossing_reaches(fC, fN, m, a.shift_row, ythr, a.hd);
+      if (P >= 3 && m < ye && out_wave) {
+        store_row(a.psi_out + (pz - (size_t)gx) + (size_t)m * nx, nx, x, out_lane, pC + c.dt * rate);
+        // moving-frame vote as a mask: rows at or above the shift row
+        // qualify outright; the crossing height of the row under it is
+        // taken in FP64 once, after the rows
+        if (kReduce)
+          over = over | (out_lane & (m >= a.shift_row) & (m <= ny - 2) & (fC >= T(0)) & (fN < T(0)));
       }
     }
     __syncthreads();
@@ -556,6 +560,15 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
   __syncthreads();
   finalize(ye - 1);
 
+  if (kReduce && out_wave) {
+    const int ms = a.shift_row - 1;  // the row under the shift row
+    if (ms >= y0 && ms < ye && ms <= ny - 2) {
+      const T f0 = M::tanh_(a.psi_in[pz + rowoff(ms)] * isq2);
+      const T f1 = M::tanh_(a.psi_in[pz + rowoff(ms + 1)] * isq2);
+      if (out_lane && f0 >= T(0) && f1 < T(0))
+        over |= crossing_reaches(f0, f1, ms, a.shift_row, ythr, a.hd);
+    }
+  }
   if (kReduce) {
     const bool any = __any(over && out_wave);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
