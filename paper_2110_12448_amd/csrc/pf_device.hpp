@@ -115,7 +115,9 @@ template <typename T>
 __device__ __forceinline__ void store_row(T *row, int nx, int x, bool ok, T v) {
   const __amdgpu_buffer_rsrc_t rs =
       __builtin_amdgcn_make_buffer_rsrc(row, 0, nx * (int)sizeof(T), 0x00020000);  // word 3: raw 32-bit access (gfx9 family)
-  const int off = ok ? x * (int)sizeof(T) : 0x40000000;
+  // the dropped lanes' offset 2^31 lies past every record: nx * 8 < 2^31
+  // because the x-y plane is at most 2^30 - 1 cells and ny >= 4
+  const int off = ok ? x * (int)sizeof(T) : (int)0x80000000u;
   if constexpr (sizeof(T) == 4) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rs, off, 0, 0);
   } else {
