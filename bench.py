@@ -600,7 +600,7 @@ def main():
     if args.launch_sample is None:
         args.launch_sample = min(400, args.steps)
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
