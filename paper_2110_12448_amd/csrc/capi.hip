@@ -40,10 +40,9 @@ constexpr double kA2 = 47.0 / 75.0;
 // work below it, so fewer, longer segments cost less, while more waves per
 // SIMD hide more latency.  With R = strips * ny / SIMDs rows per SIMD, k =
 // round(R^0.4) in FP32 and round(0.75 R^0.4) in FP64 (at most 3 waves of
-// the FP64 kernel fit a SIMD), within [1, 64]: fitted to sweeps of k on 256^2 ..
-// 8192^2 lattices, where it is the fastest k or within 2% of it (256^2: 1,
-// 1024x2048: 4, 4096^2: 9; against 4.5 rounds of fixed 8-row segments on
-// 1024x2048, 4% faster, and 14-64% on 256^2 .. 1024^2).
+// the FP64 kernel fit a SIMD), within [1, 64]: fitted to sweeps of k on
+// 256^2 .. 8192^2 lattices (1024x2048: 4 waves per SIMD); on the lattices
+// measured it is within 5% of the fastest k, which pf_autotune finds.
 int default_seg2d(int nx, int ny, int precision, int ncu) {
   const double strips = (nx + 59) / 60;
   const double R = strips * ny / (4.0 * std::max(1, ncu));
