@@ -114,6 +114,12 @@ WORKLOADS = {
 }
 
 
+# counter summary of the batched step kernel (64 solves, 32-row segments)
+BATCH_COUNTERS = dict(
+    sources=["paper_2110_12448_amd/csrc/step2d.hip", "paper_2110_12448_amd/csrc/pf_device.hpp"],
+    counters="profiles/batch2d_64solves_counters.json")
+
+
 def bench_batched(args):
     """64 uneven 2D solves (sides 256..1024) stepped by one launch per step
     (HIP graph of 10 launches), against the same solves stepped one at a time
@@ -137,10 +143,16 @@ def bench_batched(args):
         return e0.elapsed_time(e1) / 1e3
 
     ss = [pfiso.Solver(p, precision=pfiso.PF_F32) for p in prs]
+    if args.batch_rows:
+        # one fixed segment length for every member (profiling runs)
+        for s in ss:
+            s.tune(args.batch_rows, 1)
     b = pfiso.Batch(ss, graph_steps=10)
     b.step(warm)
     t_default = timed(lambda: b.step(steps))
-    seg = b.autotune(20)
+    seg = args.batch_rows or b.autotune(20)
+    print("bench: batched2d %d solves FP32, warmup %d, steps %d, geometry (%d, 1)" %
+          (len(prs), warm, steps, seg), file=sys.stderr, flush=True)
     b.step(warm)
     t = timed(lambda: b.step(steps))
     batched = cells * steps / t
@@ -163,7 +175,8 @@ def bench_batched(args):
                                   "misorientation uniform in [0,45] deg, S-bar_{2,1}, one launch "
                                   "per step replayed from a HIP graph", "solves": len(prs),
                       "cells": cells},
-           "autotuned_rows_per_segment": seg,
+           "autotuned_rows_per_segment": seg if not args.batch_rows else None,
+           "rows_per_segment": seg,
            "default_segment_value": cells * steps / t_default,
            "one_at_a_time_f32": cells * solo_steps / t32,
            "one_at_a_time_f64": cells * (solo_steps // 2) / t64}
@@ -171,11 +184,14 @@ def bench_batched(args):
     # algorithmic traffic per cell-update
     tfl = ALG_FLOPS_2D * batched / 1e12
     gbs = ALG_BYTES_2D_F32 * batched / 1e9
+    ctr = load_counters(BATCH_COUNTERS, (seg, 1))
     out["roofline"] = {"bound": "alu", "achieved": round(tfl, 3), "peak": PEAK_FP32_TFLOPS,
                        "unit": "TFLOP/s", "frac": round(tfl / PEAK_FP32_TFLOPS, 4),
                        "frac_of_nonpacked_fp32": round(tfl / PEAK_FP32_NONPACKED_TFLOPS, 4),
-                       "traffic": None, "kernel": "batch2d_kernel<float,frozen>",
+                       "traffic": None if ctr is None else ctr["hbm_bytes_per_launch"],
+                       "kernel": "batch2d_kernel<float,frozen>",
                        "kernel_ms": round(t / steps * 1e3, 5),
+                       "counters_kernel_ns": None if ctr is None else ctr["avg_duration_ns"],
                        "hbm_algorithmic_GBs": round(gbs, 1),
                        "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)}
     print(json.dumps(out))
@@ -570,6 +586,9 @@ def main():
     ap.add_argument("--no-serve-baselines", action="store_true",
                     help="serve: skip the one-at-a-time FP32/FP64 runs of the same trace")
     ap.add_argument("--hbm-budget-gib", type=float, default=2.0)
+    ap.add_argument("--batch-rows", type=int, default=0,
+                    help="batched2d: one fixed segment length for every member instead of "
+                         "pf_batch_autotune (profiling runs)")
     ap.add_argument("--schemes", default="S10,S21,Sbar21",
                     help="schemes2d: schemes to run (S21 is the reported one)")
     ap.add_argument("--diffusion-sizes", default="8192x8192,1024x2048",
