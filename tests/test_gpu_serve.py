@@ -40,3 +40,21 @@ def test_served_equals_alone(policy):
         assert np.array_equal(r.fields[2], psi) and np.array_equal(r.fields[1], U), q.rid
     summ = serve.summarize(res, max(r.finished for r in res), srv.busy_s)
     assert summ["p99_latency_s"] >= summ["p50_latency_s"] > 0
+
+
+@pytest.mark.parametrize("shape", [(256, 256), (512, 768), (1024, 1024), (1024, 2048), (2048, 2048)])
+def test_wave_estimate_matches_library_default(shape):
+    """serve.estimated_waves restates the library's default 2D geometry (k
+    waves per SIMD, k = round(R^0.4)): it must give the waves the library
+    actually launches for a solve on its own."""
+    import torch
+    from paper_2110_12448_amd import pfiso, serve
+    from paper_2110_12448_amd import workloads as wl
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    pr = wl.problem(2, shape, noise=0.0)
+    s = pfiso.Solver(pr, precision=pfiso.PF_F32)
+    k = -s.geometry()[0]
+    s.close()
+    strips = -(-shape[0] // 60)
+    nsegs = max(1, min(shape[1], k * 4 * cus // strips))
+    assert serve.estimated_waves(pr, cus=cus) == strips * nsegs
