@@ -97,3 +97,38 @@ def test_grown_solid_carries_its_seed_grain():
             assert np.all(g[solid & (X < 15.0)] == 1) and np.all(g[solid & (X > 23.5)] == 2)
         else:
             assert np.array_equal(g, g0) and np.any(g[solid] == 0)
+
+
+# face order of the tie rule: -x, +x, -y, +y, -z, +z; array axes are (z, y, x)
+_FACES = [(0, 0, -1), (0, 0, 1), (0, -1, 0), (0, 1, 0), (-1, 0, 0), (1, 0, 0)]
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("bc", [oracle.NOFLUX, oracle.PERIODIC])
+def test_tie_goes_to_the_first_face(dim, bc):
+    """A liquid cell with two solid face neighbours of exactly equal psi takes
+    the grain of the one that comes first in -x, +x, -y, +y, -z, +z, for every
+    pair of faces; a strictly larger psi wins whatever its place."""
+    faces = _FACES[:2 * dim]
+    shape = (5, 5, 5) if dim == 3 else (5, 5)
+    c = (2, 2, 2) if dim == 3 else (2, 2)
+    p = oracle.Params(dim=dim, nx=5, ny=5, nz=5 if dim == 3 else 1, bc=(bc,) * 3,
+                      dynamic_grains=1)
+
+    def cell(f):
+        off = f if dim == 3 else f[1:]
+        return tuple(ci + oi for ci, oi in zip(c, off))
+
+    for a in range(len(faces)):
+        for b in range(a + 1, len(faces)):
+            psi = np.full(shape, -1.0)
+            g = np.zeros(shape, dtype=np.int8)
+            psi[cell(faces[a])] = 0.5
+            psi[cell(faces[b])] = 0.5
+            g[cell(faces[a])] = 1 + a
+            g[cell(faces[b])] = 1 + b
+            gn = oracle.grain_update(p, psi, g)
+            assert gn[c] == 1 + a, (faces[a], faces[b], gn[c])
+            psi[cell(faces[b])] = 0.5 + 2.0 ** -20      # b strictly larger
+            gn = oracle.grain_update(p, psi, g)
+            assert gn[c] == 1 + b, (faces[a], faces[b], gn[c])
