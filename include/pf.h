@@ -138,25 +138,46 @@ const char *pf_last_error(void);
 
 /* Explicit stability limit used by pf_create: h^2 / (2 dim max(D~, 1/F1_min))
  * with F1_min the smallest F1 of Eq. Thermal_F1 over the initial lattice
- * (1 when isothermal), the paper's rule of Sec. 4.3.1 / 6.2.1 with the
- * psi-equation diffusivity included.  Returns a negative value on bad input. */
+ * (1 when isothermal).  This is the paper's rule for explicit Euler
+ * (Sec. 4.3.1 and 6.2.1: dt = 0.8 h^2 / (2 dim D~) at 0.8 of the limit)
+ * extended by the isotropic diffusivity 1/F1 of the psi equation (Eq. PF_a
+ * divided by a_s^2 F1).  It leaves out the anisotropic interface stiffness,
+ * which lowers the limit when the psi diffusivity binds (isothermal, D~ =
+ * 0.5, eps4 = 0.06: 0.95 of this limit goes unstable, 0.8 does not): keep dt
+ * at the default 0.8 of this limit when eps4 is large.  F1 changes
+ * as zeta = y + s h - y0 - Vp t moves; pf_tip_state re-checks the limit for
+ * the current s and t.  Returns a negative value on bad input. */
 double pf_stable_dt(const pf_params *p);
 
 /* Device bytes pf_create needs when the caller provides the memory. */
 size_t pf_workspace_bytes(const pf_params *p);
 
 /* Create a solver on `stream` (a hipStream_t; NULL for the null stream) of
- * the current device.  Copies p, p->grain_rot and the init arrays; the caller
- * keeps ownership of every host pointer.  If `workspace` is non-NULL it is
- * caller-owned device memory of at least pf_workspace_bytes(p) bytes, 256-byte
- * aligned, that must outlive the solver; otherwise the library allocates and
- * pf_destroy frees.  Validates the parameters (PF_ERR_ARG), dt against
- * pf_stable_dt (PF_ERR_UNSTABLE_DT) and the init arrays (PF_ERR_NONFINITE). */
+ * the current device for the problem of Sec. 2.1: psi and U evolve by Eqs.
+ * PF_a and PF_b (phi = tanh(psi / sqrt2)), with the anti-trapping current of
+ * Eq. Anti_approx (or Eq. Anti_convention, 2D), the coupling lambda = a1
+ * W/d0 = D~/a2 unless given, frozen temperature by Eqs. Thermal_F1 and
+ * Thermal_F2 when lT > 0, and the cubic anisotropy of Eq. anis_function
+ * rotated per grain by p->grain_rot; the operators are the shell mixes of
+ * Eqs. tau_2D / tau_3D with the scheme's weights (Sec. 3, 5, App. A).  Copies
+ * p, p->grain_rot and the init arrays; the caller keeps ownership of every
+ * host pointer.  If `workspace` is non-NULL it is caller-owned device memory
+ * of at least pf_workspace_bytes(p) bytes, 256-byte aligned, that must
+ * outlive the solver; otherwise the library allocates and pf_destroy frees.
+ * Validates the parameters (PF_ERR_ARG), dt against pf_stable_dt
+ * (PF_ERR_UNSTABLE_DT) and the init arrays (PF_ERR_NONFINITE); *out is set
+ * only on success. */
 int pf_create(const pf_params *p, const pf_init *init, void *workspace,
               size_t workspace_bytes, void *stream, pf_solver **out);
 
-/* Enqueue nsteps (>= 0) time steps on the solver's stream; returns without
- * waiting.  Non-finite values surface at the next pf_tip_state. */
+/* Enqueue nsteps (>= 0) explicit Euler time steps (Sec. 4.3.1 and 6.2.1):
+ * psi^{n+1} = psi^n + dt R_psi(psi^n, U^n) from Eq. PF_a, then U^{n+1} = U^n +
+ * dt R_U(psi^n, U^n, d psi/dt) from Eq. PF_b, every coefficient at level n,
+ * one fused kernel launch per step on the solver's stream; with the moving
+ * frame the tip of phi^n decides whether level n+1 moves down one row.
+ * Returns without waiting; non-finite values surface at the next
+ * pf_tip_state.  PF_ERR_ARG for nsteps < 0, PF_ERR_DEVICE when a launch
+ * fails. */
 int pf_step(pf_solver *s, int64_t nsteps);
 
 /* Enqueue nsteps steps of the solute-diffusion part of Eq. PF_b alone, with
@@ -173,13 +194,22 @@ int pf_step_diffusion(pf_solver *s, int64_t nsteps);
 int pf_synchronize(pf_solver *s);
 
 /* Synchronise and copy the state to host FP64 arrays of nx*ny*nz values in
- * frame coordinates: phi = tanh(psi/sqrt2), U, psi.  Any pointer may be NULL.
- * grain (int8) likewise. */
+ * frame coordinates (x fastest): phi = tanh(psi/sqrt2), the change of
+ * variable of Sec. 2.1 (phi = +1 solid, -1 liquid), U, and psi itself.  Any
+ * pointer may be NULL; grain (int8, the current map) likewise.  The caller
+ * owns the arrays.  PF_ERR_DEVICE when a copy fails. */
 int pf_read_fields(pf_solver *s, double *phi, double *U, double *psi, int8_t *grain);
 
-/* Synchronise, reduce the current state on the device (tip of phi, solid
- * fraction, non-finite check; FP64 accumulation) and fill *out.  Returns
- * PF_ERR_NONFINITE (with *out filled) when the state holds NaN or Inf. */
+/* Synchronise, reduce the current state on the device and fill *out: the
+ * tip, the most advanced solid-liquid interface along y (Sec. 4.3.2 and
+ * 6.2.1), as the largest height y = (j + phi_j / (phi_j - phi_{j+1})) h of a
+ * phi = 0 crossing between vertically adjacent cells (phi_j >= 0 > phi_{j+1};
+ * ties to the smallest linear index), with its x and z; the solid fraction
+ * (1/N) sum (1 + phi)/2; and a non-finite check.  Accumulation is FP64.
+ * Returns PF_ERR_NONFINITE (with *out filled) when the state holds NaN or
+ * Inf, and PF_ERR_UNSTABLE_DT (with *out filled) when, for the frame shift s
+ * and time t now reached, F1 of Eq. Thermal_F1 is no longer positive over the
+ * lattice or dt exceeds pf_stable_dt's limit with that F1. */
 int pf_tip_state(pf_solver *s, pf_tip *out);
 
 /* Device pointers of the current psi and U arrays (element type per

@@ -104,14 +104,24 @@ void weights_of(const pf_params *p, double w[3]) {
   }
 }
 
-// smallest F1 of Eq. Thermal_F1 over the lattice at t = 0 (1 if isothermal)
-double f1_min(const pf_params *p) {
+// smallest F1 of Eq. Thermal_F1 over the lattice rows for the zeta offset
+// off = s h - y0 - Vp t (zeta = y + off is linear in y, so the extreme rows
+// bound it); 1 if isothermal
+double f1_min_at(const pf_params *p, double off) {
   if (!(p->lT > 0.0)) return 1.0;
-  double zmax = (p->ny - 1) * p->h - p->y0;
-  double zmin = -p->y0;
+  double zmax = (p->ny - 1) * p->h + off;
+  double zmin = off;
   double a = 1.0 - (1.0 - p->k) * zmax / p->lT;
   double b = 1.0 - (1.0 - p->k) * zmin / p->lT;
   return a < b ? a : b;
+}
+
+// at t = 0 with no frame shift
+double f1_min(const pf_params *p) { return f1_min_at(p, -p->y0); }
+
+// explicit limit h^2 / (2 dim max(D~, 1/F1_min))
+double stable_dt_for(const pf_params *p, double f1) {
+  return p->h * p->h / (2.0 * p->dim * std::max(p->D, 1.0 / f1));
 }
 
 int max_step_blocks(const pf_params *p, int seg, int ztile) {
@@ -310,6 +320,9 @@ Coef<T> coef_of(const pf_solver *s) {
     c.k2a = (T)(s->w[1] / (4.0 * h2) * 3.0 / 16.0);
     c.k2b = (T)(s->w[1] / (4.0 * h2) / 32.0);
     c.k3 = (T)(s->w[2] / (4.0 * h2) / 8.0);
+    c.ac_eps = (T)(4e-12 * h2);
+    c.f3_eps = (T)(16e-12 * h2);
+    c.f3_scale = (T)(1.0 / (4.0 * h2));
   }
   return c;
 }
@@ -442,7 +455,9 @@ int reduce_impl(pf_solver *s, TipResult *res, FrameState *fr) {
   a.U = field<T>(s, s->L.U[s->cur]);
   a.nx = s->p.nx; a.ny = s->p.ny; a.nz = s->p.dim == 3 ? s->p.nz : 1;
   a.hd = s->p.h;
+  a.rows = 0;  // set by the launcher
   a.frame = reinterpret_cast<const FrameState *>(s->ws + s->L.frame[s->fcur]);
+  a.pending = 0;
   a.red = Reduce{reinterpret_cast<TipAcc *>(s->ws + s->L.partials),
                  reinterpret_cast<unsigned *>(s->ws + s->L.counter),
                  reinterpret_cast<TipResult *>(s->ws + s->L.result)};
@@ -860,9 +875,7 @@ const char *pf_last_error(void) { return g_err.c_str(); }
 
 double pf_stable_dt(const pf_params *p) {
   if (validate(p) != PF_OK) return -1.0;
-  double f1 = f1_min(p);
-  double diff = std::max(p->D, 1.0 / f1);
-  return p->h * p->h / (2.0 * p->dim * diff);
+  return stable_dt_for(p, f1_min(p));
 }
 
 size_t pf_workspace_bytes(const pf_params *p) {
@@ -1054,6 +1067,21 @@ int pf_tip_state(pf_solver *s, pf_tip *out) {
   }
   *out = t;
   if (r.bad) return fail(PF_ERR_NONFINITE, "state holds NaN or Inf values");
+  if (p.lT > 0.0) {
+    // the thermal coordinate has moved with the frame shift and the clock:
+    // F1 must stay positive and dt within the limit it sets
+    const double f1 = f1_min_at(&p, (double)t.frame_shift * p.h - p.y0 - p.Vp * t.t);
+    if (!(f1 > 0.0))
+      return fail(PF_ERR_UNSTABLE_DT, "F1 = 1 - (1-k) zeta / lT is no longer positive over the "
+                                      "lattice (frame shift " + std::to_string(t.frame_shift) +
+                                      ", t = " + std::to_string(t.t) + ")");
+    const double dtmax = stable_dt_for(&p, f1);
+    if (s->dt > dtmax * (1.0 + 1e-12))
+      return fail(PF_ERR_UNSTABLE_DT, "dt = " + std::to_string(s->dt) +
+                                          " now exceeds the stability limit " +
+                                          std::to_string(dtmax) + " (F1 min " +
+                                          std::to_string(f1) + ")");
+  }
   return PF_OK;
 }
 

@@ -56,11 +56,13 @@ struct Coef {
   T h;
   T cT;             // two-point <10> faces: 1/(2h^2) (2D)
   T at_eps;         // 1e-12 h^2: the |g|^2 <= 1e-12 guard for h g (face gradients, 2D)
-  T ac_eps;         // 4e-12 h^2: the same guard for 2h g (centre differences, 2D)
+  T ac_eps;         // 4e-12 h^2: the same guard for 2h g (centre differences)
   T an1, an8;       // 1 + eps4, 8 eps4 (2D a_s = 1 + eps4 - 8 eps4 u^2 v^2)
   T k1a, k1b;       // cD1/4, cD1/16: <100> link alpha weights times the shell coefficient (3D)
   T k2a, k2b;       // 3 cD2/16, cD2/32: the same for <110> links (3D)
   T k3;             // cD3/8: <111> links, mean of the 8 cube corners (3D)
+  T f3_eps;         // 16e-12 h^2: the |g|^2 <= 1e-12 guard for 4h g (face gradients, 3D)
+  T f3_scale;       // 1/(4 h^2): unscales the sum of the 4h-scaled face fluxes (3D)
 };
 
 template <typename T>
@@ -116,8 +118,10 @@ template <typename T>
 struct ReduceArgs {
   const T *psi, *U;
   int nx, ny, nz;
+  int rows;                 // rows per column walk (reduce_geometry)
   double hd;
-  const FrameState *frame;  // pending shift of the arrays read
+  const FrameState *frame;  // pending shift of the arrays read, or NULL:
+  int pending;              // then this host value is used
   Reduce red;
 };
 
@@ -137,6 +141,13 @@ Geom3D geom3d(int nx, int ny, int nz, int seg, int ztile);
 size_t step3d_lds_bytes(int ztile, size_t elem);
 
 size_t tip_acc_bytes();
+// Launch geometry of the reduction: rows per column walk and workgroups
+// (256 threads; at most kMaxReduceBlocks).
+constexpr int kMaxReduceBlocks = 4096;
+struct GeomReduce {
+  int rows, blocks;
+};
+GeomReduce reduce_geometry(int nx, int ny, int nz);
 int reduce_blocks(int nx, int ny, int nz);
 
 // Divergence / anti-trapping variants of the 2D step.

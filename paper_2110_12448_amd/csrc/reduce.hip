@@ -7,6 +7,18 @@
 // interpolation; the largest y wins, ties go to the smallest linear index.
 // Solid fraction: (1/N) sum (1 + phi)/2.  All accumulation in FP64; phi itself
 // is evaluated in the field precision exactly as the step kernels do.
+//
+// Schedule: each wave64 walks up 64 adjacent columns of one z layer over a
+// run of `rows` rows, loading psi and U once per cell and evaluating tanh
+// once per cell (phi of the row above is carried to the next row; a run
+// evaluates one extra row above its end for the last crossing test).  The
+// walk has no branch: per column the highest crossing row of the run is kept
+// by selects and its FP64 height formed once at the end of the run.  Runs
+// are ordered strip-fastest, so consecutive waves read adjacent 256-byte row
+// pieces; the grid holds up to kMaxReduceBlocks workgroups of 4 waves and
+// strides over the runs.  Per-wave FP64 partials are combined by wave
+// shuffles, per workgroup, then by the last workgroup to finish, in
+// workgroup order (deterministic for a given lattice).
 #include "pf_device.hpp"
 
 namespace pf {
@@ -17,34 +29,68 @@ template <typename T>
 __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs<T> a) {
   using M = Math<T>;
   const int nx = a.nx, ny = a.ny, nz = a.nz;
-  const int pend = a.frame->pending;
-  const int lines = ny * nz;
+  const int pend = a.frame ? a.frame->pending : a.pending;
+  const int lane = threadIdx.x & 63;
+  const int wpb = blockDim.x >> 6;
+  const long long wave = (long long)blockIdx.x * wpb + (threadIdx.x >> 6);
+  const long long nwaves = (long long)gridDim.x * wpb;
+  const int nstrips = (nx + 63) >> 6;
+  const int rows = a.rows;
+  const int nsegs = (ny + rows - 1) / rows;
+  const long long items = (long long)nstrips * nsegs * nz;
   const T isq2 = T(0.70710678118654752);
+  const size_t plane = (size_t)nx * (size_t)ny;
   TipAcc acc;
   tip_init(acc);
-  for (int line = blockIdx.x; line < lines; line += gridDim.x) {
-    const int j = line % ny;
-    const int l = line / ny;
-    const int jp = pend ? min(j + 1, ny - 1) : j;
-    const int jq = pend ? min(j + 2, ny - 1) : j + 1;
-    const size_t base = (size_t)l * (size_t)ny * (size_t)nx;
-    for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-      T p = a.psi[base + (size_t)jp * nx + x];
-      T u = a.U[base + (size_t)jp * nx + x];
-      T f = M::tanh_(p * isq2);
-      double fd = (double)f;
-      acc.fs += 0.5 * (1.0 + fd);
-      acc.bad += (M::finite(p) && M::finite(u)) ? 0u : 1u;
-      if (j <= ny - 2 && f >= T(0)) {
-        T fn = M::tanh_(a.psi[base + (size_t)jq * nx + x] * isq2);
-        if (fn < T(0)) {
-          double fnd = (double)fn;
-          double yy = ((double)j + fd / (fd - fnd)) * a.hd;
-          long long id = (long long)x + (long long)nx * ((long long)j + (long long)ny * l);
-          if (yy > acc.y || (yy == acc.y && id < acc.idx)) {
-            acc.y = yy;
-            acc.idx = id;
-          }
+  // stored row of frame row j (a pending shift reads one row up, the top
+  // row repeated)
+  auto srow = [&](int j) -> size_t { return (size_t)(pend ? min(j + 1, ny - 1) : j) * nx; };
+  for (long long it = wave; it < items; it += nwaves) {
+    const int strip = (int)(it % nstrips);
+    const long long r2 = it / nstrips;
+    const int seg = (int)(r2 % nsegs);
+    const int l = (int)(r2 / nsegs);
+    const int x = strip * 64 + lane;
+    const bool in = x < nx;
+    const size_t base = (size_t)l * plane + (size_t)(in ? x : nx - 1);
+    const int y0 = seg * rows;
+    const int ye = min(y0 + rows, ny);
+    T p = a.psi[base + srow(y0)];
+    T f = M::tanh_(p * isq2);
+    // per column the highest crossing row wins: crossing heights lie in
+    // [j, j + 1) h, so a higher row is always further up; the loop keeps
+    // that row and its two phi values with selects (no branch) and the FP64
+    // height is formed once per run
+    int bj = -1;
+    T bf = T(0), bfn = T(0);
+    double sf = 0.0;
+    unsigned bad = 0u;
+#pragma unroll 4
+    for (int j = y0; j < ye; ++j) {
+      const T u = a.U[base + srow(j)];
+      const bool up = j + 1 < ny;
+      const T pn = a.psi[base + srow(up ? j + 1 : j)];
+      const T fn = M::tanh_(pn * isq2);
+      sf += (double)f;
+      bad += (M::finite(p) && M::finite(u)) ? 0u : 1u;
+      const bool cr = up && f >= T(0) && fn < T(0);
+      bj = cr ? j : bj;
+      bf = cr ? f : bf;
+      bfn = cr ? fn : bfn;
+      p = pn;
+      f = fn;
+    }
+    if (in) {
+      // sum over the run of (1 + phi)/2
+      acc.fs += 0.5 * ((double)(ye - y0) + sf);
+      acc.bad += bad;
+      if (bj >= 0) {
+        const double fd = (double)bf, fnd = (double)bfn;
+        const double yy = ((double)bj + fd / (fd - fnd)) * a.hd;
+        const long long id = (long long)x + (long long)nx * ((long long)bj + (long long)ny * l);
+        if (yy > acc.y || (yy == acc.y && id < acc.idx)) {
+          acc.y = yy;
+          acc.idx = id;
         }
       }
     }
@@ -64,16 +110,25 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs<T> a) {
 
 size_t tip_acc_bytes() { return sizeof(TipAcc); }
 
-int reduce_blocks(int nx, int ny, int nz) {
-  (void)nx;
-  long long lines = (long long)ny * nz;
-  return (int)(lines < 256 ? lines : 256);  // one block per CU: few grid-wide fences
+// Runs of 32 rows, halved (down to 4) until there are 8192 of them (8 waves
+// per SIMD on 256 CUs), so small lattices still spread over the chip.
+GeomReduce reduce_geometry(int nx, int ny, int nz) {
+  const long long cols = (long long)((nx + 63) / 64) * nz;
+  int rows = 32;
+  while (rows > 4 && cols * ((ny + rows - 1) / rows) < 8192) rows /= 2;
+  const long long items = cols * ((ny + rows - 1) / rows);
+  const long long blocks = (items + 3) / 4;
+  return GeomReduce{rows, (int)(blocks < kMaxReduceBlocks ? blocks : kMaxReduceBlocks)};
 }
+
+int reduce_blocks(int nx, int ny, int nz) { return reduce_geometry(nx, ny, nz).blocks; }
 
 template <typename T>
 hipError_t launch_reduce(const ReduceArgs<T> &a, hipStream_t st) {
-  int blocks = reduce_blocks(a.nx, a.ny, a.nz);
-  hipLaunchKernelGGL((reduce_kernel<T>), dim3(blocks), dim3(256), 0, st, a);
+  const GeomReduce g = reduce_geometry(a.nx, a.ny, a.nz);
+  ReduceArgs<T> b = a;
+  b.rows = g.rows;
+  hipLaunchKernelGGL((reduce_kernel<T>), dim3(g.blocks), dim3(256), 0, st, b);
   return hipGetLastError();
 }
 

@@ -42,8 +42,6 @@ namespace pf {
 
 namespace {
 
-constexpr float kGradEps3 = 1e-12f;
-
 template <typename T>
 struct Rot3 {
   T m[9];  // row-major crystal -> lab
@@ -51,10 +49,14 @@ struct Rot3 {
 
 // a_s and, optionally, one lab component of J = a^2 g + |g|^2 a da/dg
 // (J = R [g'(a^2 - 16 eps4 a s4) + 16 eps4 a g'^3/|g|^2], g' = R^T g).
+// a_s is scale-free and J homogeneous of degree 1, so callers pass a scaled
+// gradient (4h g at faces, 2h g at the centre) with the |g|^2 <= 1e-12 guard
+// scaled alike (eps), and unscale J once.
 template <typename T, int comp>
-__device__ __forceinline__ T aniso3(T gx, T gy, T gz, const Rot3<T> &R, const Coef<T> &c) {
+__device__ __forceinline__ T aniso3(T gx, T gy, T gz, const Rot3<T> &R, const Coef<T> &c,
+                                    T eps) {
   T g2 = gx * gx + gy * gy + gz * gz;
-  T r2 = Math<T>::rcp(g2 > T(kGradEps3) ? g2 : T(kGradEps3));
+  T r2 = Math<T>::rcp(g2 > eps ? g2 : eps);
   T c0 = R.m[0] * gx + R.m[3] * gy + R.m[6] * gz;
   T c1 = R.m[1] * gx + R.m[4] * gy + R.m[7] * gz;
   T c2 = R.m[2] * gx + R.m[5] * gy + R.m[8] * gz;
@@ -62,7 +64,7 @@ __device__ __forceinline__ T aniso3(T gx, T gy, T gz, const Rot3<T> &R, const Co
   T s4 = (q0 * q0 + q1 * q1 + q2 * q2) * (r2 * r2);
   T a = c.an0 + c.an4 * s4;
   if constexpr (comp < 0) {
-    return g2 > T(kGradEps3) ? a : T(1);
+    return g2 > eps ? a : T(1);
   } else {
     T t = c.an16 * a;
     T base = a * a - t * s4;
@@ -72,7 +74,7 @@ __device__ __forceinline__ T aniso3(T gx, T gy, T gz, const Rot3<T> &R, const Co
     T j2 = c2 * (base + tr * q2);
     T j = R.m[3 * comp + 0] * j0 + R.m[3 * comp + 1] * j1 + R.m[3 * comp + 2] * j2;
     T plain = comp == 0 ? gx : (comp == 1 ? gy : gz);
-    return g2 > T(kGradEps3) ? j : plain;
+    return g2 > eps ? j : plain;
   }
 }
 
@@ -203,7 +205,7 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
 
   // own-row window (rows r-2, r-1, r) and carries
   T pS = 0, pC = 0, pN = 0, uS = 0, uC = 0, uN = 0, fS = 0, fC = 0, fN = 0;
-  T aAown[3] = {0, 0, 0};  // alpha_A of own cell at rows m-1, m (index by m mod 3)
+  T aAq = 0, aAm = 0;      // alpha_A of own cell at rows m-1 and m
   T FyS = 0;               // y face flux below row r-1
   int gS = 0, gC = 0, gN = 0;
   // shared divergence links: P_y of the next row (fields D, A), the south
@@ -266,16 +268,16 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
     }
     const int m = r - 1;
     const int sm1 = slot5(m - 1), s0 = slot5(m), sp1 = slot5(m + 1);
-    const T ih = c.inv_h, qh = T(0.25) * c.inv_h;
 
     if constexpr (P == 1) {
-      // only the y face between rows m and m+1 (lower cell (x, m, z))
-      T gyn = (L(kPsi, sp1, zi, 0) - L(kPsi, s0, zi, 0)) * ih;
-      T gxt = (L(kPsi, s0, zi, 1) + L(kPsi, sp1, zi, 1) - L(kPsi, s0, zi, -1) -
-               L(kPsi, sp1, zi, -1)) * qh;
-      T gzt = (L(kPsi, s0, zi + 1, 0) + L(kPsi, sp1, zi + 1, 0) - L(kPsi, s0, zi - 1, 0) -
-               L(kPsi, sp1, zi - 1, 0)) * qh;
-      FyS = aniso3<T, 1>(gxt, gyn, gzt, rot_of(gC), c);
+      // only the y face between rows m and m+1 (lower cell (x, m, z)), in
+      // the same form as the steady state's north face
+      const T cx0 = L(kPsi, s0, zi, 1) - L(kPsi, s0, zi, -1);
+      const T cx1 = L(kPsi, sp1, zi, 1) - L(kPsi, sp1, zi, -1);
+      const T cz0 = L(kPsi, s0, zi + 1, 0) - L(kPsi, s0, zi - 1, 0);
+      const T cz1 = L(kPsi, sp1, zi + 1, 0) - L(kPsi, sp1, zi - 1, 0);
+      FyS = aniso3<T, 1>(cx0 + cx1, T(4) * (L(kPsi, sp1, zi, 0) - L(kPsi, s0, zi, 0)), cz0 + cz1,
+                         rot_of(gC), c, c.f3_eps);
       __syncthreads();
       return;
     } else {
@@ -319,44 +321,41 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
         G += c.cG3 * g3;
       }
       const Rot3<T> R = rot_of(gC);
-      const T hh = T(0.5) * c.inv_h;
-      T ac = aniso3<T, -1>((Pn[nb(1, 0, 0)] - Pn[nb(-1, 0, 0)]) * hh,
-                           (Pn[nb(0, 1, 0)] - Pn[nb(0, -1, 0)]) * hh,
-                           (Pn[nb(0, 0, 1)] - Pn[nb(0, 0, -1)]) * hh, R, c);
-      // x face east of the cell
-      T FxE = aniso3<T, 0>(
-          (Pn[nb(1, 0, 0)] - p0) * ih,
-          (Pn[nb(0, 1, 0)] + Pn[nb(1, 1, 0)] - Pn[nb(0, -1, 0)] - Pn[nb(1, -1, 0)]) * qh,
-          (Pn[nb(0, 0, 1)] + Pn[nb(1, 0, 1)] - Pn[nb(0, 0, -1)] - Pn[nb(1, 0, -1)]) * qh, R, c);
+      // central differences (2h g at the centre); the face gradients below
+      // are 4h g: the normal difference times 4 and, for each tangential
+      // axis, the sum of the central differences of the two cells
+      const T cx = Pn[nb(1, 0, 0)] - Pn[nb(-1, 0, 0)];
+      const T cy = Pn[nb(0, 1, 0)] - Pn[nb(0, -1, 0)];
+      const T cz = Pn[nb(0, 0, 1)] - Pn[nb(0, 0, -1)];
+      T ac = aniso3<T, -1>(cx, cy, cz, R, c, c.ac_eps);
+      // x face east of the cell (the right lane's differences by DPP)
+      T FxE = aniso3<T, 0>(T(4) * (Pn[nb(1, 0, 0)] - p0), cy + from_right(cy),
+                           cz + from_right(cz), R, c, c.f3_eps);
       T FxW = from_left(FxE);
       // y face north of the cell
-      T FyN = aniso3<T, 1>(
-          (Pn[nb(1, 0, 0)] + Pn[nb(1, 1, 0)] - Pn[nb(-1, 0, 0)] - Pn[nb(-1, 1, 0)]) * qh,
-          (Pn[nb(0, 1, 0)] - p0) * ih,
-          (Pn[nb(0, 0, 1)] + Pn[nb(0, 1, 1)] - Pn[nb(0, 0, -1)] - Pn[nb(0, 1, -1)]) * qh, R, c);
+      T FyN = aniso3<T, 1>(cx + (Pn[nb(1, 1, 0)] - Pn[nb(-1, 1, 0)]),
+                           T(4) * (Pn[nb(0, 1, 0)] - p0),
+                           cz + (Pn[nb(0, 1, 1)] - Pn[nb(0, 1, -1)]), R, c, c.f3_eps);
       // z face above (own grain); the face below is the wave below's face
       // above (the same points in the same order, the grain of the lower
       // cell), read after a barrier; the lowest wave computes its own
-      T FzU = aniso3<T, 2>(
-          (Pn[nb(1, 0, 0)] + Pn[nb(1, 0, 1)] - Pn[nb(-1, 0, 0)] - Pn[nb(-1, 0, 1)]) * qh,
-          (Pn[nb(0, 1, 0)] + Pn[nb(0, 1, 1)] - Pn[nb(0, -1, 0)] - Pn[nb(0, -1, 1)]) * qh,
-          (Pn[nb(0, 0, 1)] - p0) * ih, R, c);
+      T FzU = aniso3<T, 2>(cx + (Pn[nb(1, 0, 1)] - Pn[nb(-1, 0, 1)]),
+                           cy + (Pn[nb(0, 1, 1)] - Pn[nb(0, -1, 1)]),
+                           T(4) * (Pn[nb(0, 0, 1)] - p0), R, c, c.f3_eps);
       FZ[w * 64 + lane] = FzU;
       T FzD;
       if (w == 0) {
         Rot3<T> Rd = R;
         if (kMulti) Rd = rot_of(a.grain[pzd + rowoff(m)]);
-        FzD = aniso3<T, 2>(
-            (Pn[nb(1, 0, -1)] + Pn[nb(1, 0, 0)] - Pn[nb(-1, 0, -1)] - Pn[nb(-1, 0, 0)]) * qh,
-            (Pn[nb(0, 1, -1)] + Pn[nb(0, 1, 0)] - Pn[nb(0, -1, -1)] - Pn[nb(0, -1, 0)]) * qh,
-            (p0 - Pn[nb(0, 0, -1)]) * ih, Rd, c);
+        FzD = aniso3<T, 2>((Pn[nb(1, 0, -1)] - Pn[nb(-1, 0, -1)]) + cx,
+                           (Pn[nb(0, 1, -1)] - Pn[nb(0, -1, -1)]) + cy,
+                           T(4) * (p0 - Pn[nb(0, 0, -1)]), Rd, c, c.f3_eps);
       }
       __syncthreads();
       if (w != 0) FzD = FZ[(w - 1) * 64 + lane];
       const T ac2 = ac * ac;
-      T std6 = Pn[nb(1, 0, 0)] + Pn[nb(-1, 0, 0)] + Pn[nb(0, 1, 0)] + Pn[nb(0, -1, 0)] +
-               Pn[nb(0, 0, 1)] + Pn[nb(0, 0, -1)] - T(6) * p0;
-      T Nn = (FxE - FxW + FyN - FyS + FzU - FzD) * ih - ac2 * (std6 * c.cStd);
+      // the standard Laplacian of the remainder is the <100> sum s1 / h^2
+      T Nn = (FxE - FxW + FyN - FyS + FzU - FzD) * c.f3_scale - ac2 * (s1 * c.cStd);
       FyS = FyN;
       T F1 = T(1), F2 = uC;
       if (kFrozen) {
@@ -374,7 +373,8 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
         aA = (x == -1) ? fr : ((x == nx) ? fl : aA);
       }
       sm[at(kAA, s0, zi)] = aA;
-      aAown[(m + 3) % 3] = aA;
+      aAq = aAm;
+      aAm = aA;
       // dynamic grains: the grain of row m at the next level (a liquid cell,
       // psi < 0, with a solid face neighbour takes the grain of the solid
       // neighbour with the largest psi, first of -x, +x, -y, +y, -z, +z)
@@ -538,7 +538,7 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
         // iteration ago), then let row q wait
         if (q - 1 >= y0) finalize(q - 1);
         waitU = uS;
-        waitBase = part + sq2 * aAown[(q + 3) % 3];
+        waitBase = part + sq2 * aAq;
         waitDen = M::rcp(T(1) + c.k - c.omk * fS);
       }
       southSum = fN_ + from_left(fNE) + from_right(fNW);

@@ -1,9 +1,15 @@
 """Batched 2D stepping (pf_batch_*): every solve of a batch must be bitwise
 identical to the same solve stepped on its own, with and without HIP-graph
-replay, the moving frame, multi-grain maps and interleaved single steps."""
+replay, the moving frame, multi-grain maps and interleaved single steps, and
+every member must match the FP64 oracle's explicit step (Sec. 4.3.1) on the
+same inputs: FP64 within 1e-10, FP32 within 1e-5 in phi and U, frame shifts
+equal."""
+import math
+
 import numpy as np
 import pytest
 
+import oracle
 from paper_2110_12448_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -42,7 +48,21 @@ def solo(pr, prec, nsteps):
     return psi, U, fr
 
 
-def check_batch(prs, prec, plan, graph=0):
+TOL = {0: 1e-5, 1: 1e-10}
+
+
+def against_oracle(pr, prec, nsteps, phi, U, shift):
+    p = oracle.Params.from_problem(pr)
+    opsi, oU, st = oracle.step(p, pr["psi0"], pr["U0"], pr["grain"], nsteps)
+    d = max(float(np.max(np.abs(phi - np.tanh(opsi / math.sqrt(2.0))))),
+            float(np.max(np.abs(U - oU))))
+    assert st.nonfinite == 0
+    assert shift == st.shift, (shift, st.shift)
+    assert d <= TOL[prec], (pr["nx"], pr["ny"], nsteps, d)
+    return d
+
+
+def check_batch(prs, prec, plan, graph=0, oracle_check=True):
     """plan: list of ('b', n) batch steps or ('s', i, n) single steps of solve i."""
     pf = _pf()
     print("batch of %d solves prec=%d graph=%d plan=%s" % (len(prs), prec, graph, plan), flush=True)
@@ -63,6 +83,10 @@ def check_batch(prs, prec, plan, graph=0):
         rpsi, rU, rfr = solo(pr, prec, total[i])
         assert np.array_equal(psi, rpsi) and np.array_equal(U, rU), (i, total[i])
         assert fr == rfr
+        if oracle_check:
+            d = against_oracle(pr, prec, total[i], phi, U, fr[0])
+            print("member %d %dx%d: %d steps, max diff vs oracle %.2e" %
+                  (i, pr["nx"], pr["ny"], total[i], d), flush=True)
     b.close()
     for s in ss:
         s.close()
@@ -98,3 +122,17 @@ def test_batch_of_one_replays_a_single_solve():
     frame) equals the same solve stepped launch by launch."""
     prs = problems(frame=True, thermal="frozen")[:1]
     check_batch(prs, 0, [("b", 37), ("s", 0, 2), ("b", 12)], graph=6)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_large_members_frozen_frame_graph_vs_oracle(prec):
+    """Members of 512 x 768 and 640 x 512 beside small ones, frozen gradient,
+    moving frame, graph replay (6-launch epochs) with eager work between
+    replays: 102 steps, every member against the oracle."""
+    sizes = [(512, 768), (640, 512), (96, 160), (256, 256)]
+    prs = []
+    for i, (nx, ny) in enumerate(sizes):
+        a0 = 45.0 * float(wl.uniform(4, 11, len(sizes))[i])
+        prs.append(wl.problem(2, (nx, ny), alpha0_deg=a0, seed=300 + i, frame=1,
+                              shift_row=12, seed_radius=14.0))
+    check_batch(prs, prec, [("b", 60), ("s", 3, 2), ("b", 40)], graph=6)

@@ -142,3 +142,50 @@ def test_batch_rejects_dynamic_grains():
         pf.Batch([s])
     assert e.value.code == pf.PF_ERR_ARG
     s.close()
+
+
+# face order of the tie rule: -x, +x, -y, +y, -z, +z (array axes (z, y, x))
+_FACES = [(0, 0, -1), (0, 0, 1), (0, -1, 0), (0, 1, 0), (-1, 0, 0), (1, 0, 0)]
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("prec", [1, 0])
+def test_tie_goes_to_the_first_face_gpu(dim, prec):
+    """Two solid face neighbours of exactly equal psi (0.5, exact in FP32 and
+    FP64): the liquid cell between them takes the grain of the one first in
+    -x, +x, -y, +y, -z, +z, for every pair, as the oracle does; a strictly
+    larger psi wins whatever its place."""
+    pf = _pf()
+    faces = _FACES[:2 * dim]
+    n = 6
+    shape = (n, n, n) if dim == 3 else (n, n)
+    c = (2, 2, 2) if dim == 3 else (2, 2)
+    ng = 2 * dim + 1
+    rot = (np.stack([wl.rotation_2d(11.0 * g) for g in range(ng)]) if dim == 2
+           else wl.random_rotations(77, ng))
+
+    def cell(f):
+        off = f if dim == 3 else f[1:]
+        return tuple(ci + oi for ci, oi in zip(c, off))
+
+    for a in range(len(faces)):
+        for b in range(a + 1, len(faces)):
+            for bigger in (0.0, 2.0 ** -10):
+                pr = wl.problem(dim, (n,) * dim, thermal="isothermal", bc=(1, 1, 1), rot=rot,
+                                noise=0.0, dynamic_grains=1)
+                psi = np.full(shape, -1.0)
+                g = np.zeros(shape, dtype=np.int8)
+                psi[cell(faces[a])] = 0.5
+                psi[cell(faces[b])] = 0.5 + bigger
+                g[cell(faces[a])] = 1 + a
+                g[cell(faces[b])] = 1 + b
+                pr["psi0"], pr["grain"] = psi, g
+                pr["U0"] = np.full(shape, -0.5)
+                s = pf.Solver(pr, precision=prec)
+                s.step(1)
+                _, _, _, gn = s.read_fields()
+                s.close()
+                og = oracle.grain_update(oracle.Params.from_problem(pr), psi, g)
+                want = 1 + (b if bigger else a)
+                assert gn[c] == want == og[c], (faces[a], faces[b], bigger, gn[c], og[c])
+                assert np.array_equal(gn, og)

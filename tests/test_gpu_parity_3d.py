@@ -1,6 +1,9 @@
 """GPU parity of the 3D fused step (through the C ABI) against the FP64 CPU
 oracle on identical seeded inputs."""
+import functools
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -33,6 +36,17 @@ def run_gpu(pr, precision, nsteps, tune=None, chunks=1):
     shift = s.frame_state()
     s.close()
     return phi, U, psi, tip, shift
+
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@functools.lru_cache(maxsize=4)
+def _oracle_c3(n, nsteps):
+    pr = wl.config_polycrystal_3d(n=n)
+    p = oracle.Params.from_problem(pr)
+    psi, U, st = oracle.step(p, pr["psi0"], pr["U0"], pr["grain"], nsteps)
+    return pr, np.tanh(psi / SQ2), U, st, p
 
 
 def run_oracle(pr, nsteps, **over):
@@ -104,12 +118,62 @@ def test_edge_cases_3d(case, prec):
     assert d <= (TOL_F64 if prec == 1 else TOL_F32)
 
 
-def test_moving_frame_3d():
+@pytest.mark.parametrize("prec", [1, 0])
+def test_moving_frame_3d(prec):
+    """Moving frame in 3D over 100 steps (8 shifts; the oracle's tip stays at
+    least 5e-3 W from the shift threshold at every decision, so FP32 decides
+    as FP64 does)."""
     pr = _poly(20, ny=32, n_grains=2, frame=1, shift_row=8, seed_radius=6.0)
-    ophi, oU, _, st, p = run_oracle(pr, 40)
-    phi, U, psi, tip, (shift, pend) = run_gpu(pr, 1, 40)
-    assert st.shift >= 2 and shift == st.shift
-    assert max(_cmp(phi, ophi), _cmp(U, oU)) <= TOL_F64
+    ophi, oU, _, st, p = run_oracle(pr, 100)
+    phi, U, psi, tip, (shift, pend) = run_gpu(pr, prec, 100)
+    assert st.shift >= 5 and shift == st.shift
+    d = max(_cmp(phi, ophi), _cmp(U, oU))
+    print("max diff %.3e" % d)
+    assert d <= (TOL_F64 if prec == 1 else TOL_F32)
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_polycrystal_c3_recipe_100_steps(prec):
+    """The 256^3 polycrystal's recipe at 64^3 (8 Voronoi grains with uniform
+    random orientations, planar slab, frozen gradient, periodic x and z,
+    S-bar_{1,2,0}) for the 100 steps of the parity gate, in the benchmark's
+    launch geometry: 32-row segments of 14-row workgroups in FP32 (2 rows in
+    FP64, the most its workgroups hold).  Every cell against the oracle, and
+    the tip and solid fraction."""
+    pr, ophi, oU, st, p = _oracle_c3(64, 100)
+    tune = (32, 14) if prec == 0 else (32, 2)
+    phi, U, psi, tip, _ = run_gpu(pr, prec, 100, tune=tune)
+    d = max(_cmp(phi, ophi), _cmp(U, oU))
+    print("max diff %.3e" % d)
+    assert d <= (TOL_F64 if prec == 1 else TOL_F32)
+    ot = oracle.tip(p, ophi)
+    assert tip["found"] and abs(tip["y_frame"] - ot["y"]) <= (1e-9 if prec == 1 else 1e-3)
+    assert tip["solid_fraction"] == pytest.approx(oracle.solid_fraction(p, ophi),
+                                                  abs=1e-12 if prec == 1 else 1e-6)
+
+
+def test_tip_golden_3d_10k():
+    """Tip of a small polycrystal in the moving frame after 10^4 steps within
+    0.05 W of the oracle's, FP64 and FP32 (oracle values stored by
+    tests/golden/make_tip_golden.py, FP32 against the oracle that rounds its
+    stored fields to FP32 after every step)."""
+    gold = json.load(open(os.path.join(HERE, "golden", "tip_small_3d_10k.json")))
+    pf = _pf()
+    for case in gold["cases"]:
+        prec = pf.PF_F64 if case["round_f32"] == 0 else pf.PF_F32
+        pr = wl.config_polycrystal_3d(**gold["problem"])
+        print("gpu case: 3D tip golden prec=%d steps=%d" % (prec, gold["nsteps"]), flush=True)
+        s = pf.Solver(pr, precision=prec)
+        s.step(gold["nsteps"])
+        t = s.tip_state()
+        s.close()
+        print(case, {k: t[k] for k in ("x", "z", "y_lab", "frame_shift", "solid_fraction")})
+        assert t["frame_shift"] >= 100
+        assert abs(t["y_lab"] - case["y_lab"]) <= 0.05
+        # the oracle's own FP64 and FP32-rounded runs differ by 2.2e-4 in solid
+        # fraction after 10^4 steps
+        assert abs(t["solid_fraction"] - case["solid_fraction"]) <= (1e-6 if prec == pf.PF_F64
+                                                                      else 1e-3)
 
 
 @pytest.mark.parametrize("w", [wl.ISO_3D, wl.ISO_3D_441])

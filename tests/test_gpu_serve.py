@@ -1,7 +1,13 @@
 """Continuous-batching server: every served result is bitwise the result of
-the same request run alone; admission respects the HBM budget."""
+the same request run alone and matches the FP64 oracle's explicit step on the
+same inputs (FP64 within 1e-10, FP32 within 1e-5 in phi and U); admission
+respects the HBM budget."""
+import math
+
 import numpy as np
 import pytest
+
+import oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -38,6 +44,13 @@ def test_served_equals_alone(policy):
         phi, U, psi, _ = s.read_fields()
         s.close()
         assert np.array_equal(r.fields[2], psi) and np.array_equal(r.fields[1], U), q.rid
+        pr = q.problem
+        opsi, oU, st = oracle.step(oracle.Params.from_problem(pr), pr["psi0"], pr["U0"],
+                                   pr["grain"], q.steps)
+        d = max(float(np.max(np.abs(r.fields[0] - np.tanh(opsi / math.sqrt(2.0))))),
+                float(np.max(np.abs(r.fields[1] - oU))))
+        tol = 1e-10 if q.precision == pfiso.PF_F64 else 1e-5
+        assert st.nonfinite == 0 and d <= tol, (q.rid, q.precision, d)
     summ = serve.summarize(res, max(r.finished for r in res), srv.busy_s)
     assert summ["p99_latency_s"] >= summ["p50_latency_s"] > 0
 
