@@ -25,6 +25,14 @@ int fail(int code, const std::string &msg) {
   return code;
 }
 
+}  // namespace
+
+namespace pf {
+int report_error(int code, const char *msg) { return fail(code, msg); }
+}  // namespace pf
+
+namespace {
+
 #define PF_HIP(call)                                                          \
   do {                                                                        \
     hipError_t e_ = (call);                                                   \
@@ -130,7 +138,7 @@ int max_step_blocks(const pf_params *p, int seg, int ztile) {
 }
 
 struct Layout {
-  size_t psi[2], U[2], grain, grain2, rot, frame[3], partials, counter, result, total;
+  size_t psi[2], U[2], grain, grain2, rot, frame[3], partials, result, total;
 };
 
 Layout layout_of(const pf_params *p) {
@@ -149,7 +157,6 @@ Layout layout_of(const pf_params *p) {
   int nb = std::max(max_step_blocks(p, p->dim == 2 ? 1 : 4, 1),
                     reduce_blocks(p->nx, p->ny, p->dim == 3 ? p->nz : 1));
   L.partials = o; o += align256((size_t)(nb + 64) * tip_acc_bytes());
-  L.counter = o; o += 256;
   L.result = o; o += 256;
   L.total = o;
   return L;
@@ -459,7 +466,6 @@ int reduce_impl(pf_solver *s, TipResult *res, FrameState *fr) {
   a.frame = reinterpret_cast<const FrameState *>(s->ws + s->L.frame[s->fcur]);
   a.pending = 0;
   a.red = Reduce{reinterpret_cast<TipAcc *>(s->ws + s->L.partials),
-                 reinterpret_cast<unsigned *>(s->ws + s->L.counter),
                  reinterpret_cast<TipResult *>(s->ws + s->L.result)};
   PF_HIP(launch_reduce<T>(a, s->stream));
   PF_HIP(hipMemcpyAsync(res, a.red.result, sizeof(TipResult), hipMemcpyDeviceToHost, s->stream));
@@ -973,8 +979,7 @@ int pf_create(const pf_params *p, const pf_init *init, void *workspace, size_t w
     FrameState z{0, 0, 0};
     if (hipMemcpy(s->ws + L.frame[0], &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(s->ws + L.frame[1], &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(s->ws + L.frame[2], &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemset(s->ws + L.counter, 0, 256) != hipSuccess)
+        hipMemcpy(s->ws + L.frame[2], &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess)
       r2 = fail(PF_ERR_DEVICE, "state initialisation failed");
   }
   if (r2 != PF_OK) {

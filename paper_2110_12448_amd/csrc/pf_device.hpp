@@ -171,48 +171,41 @@ __device__ __forceinline__ void tip_wave_reduce(TipAcc &a) {
   }
 }
 
-// Block reduction of one TipAcc per wave (blockDim = 64 * nwaves <= 1024),
-// then a grid-wide finish by the last block to arrive: it reduces every
-// block's partial in block order (deterministic) and calls finish(total).
-// `lds` needs room for 16 TipAcc.
-template <typename Finish>
-__device__ __forceinline__ void tip_block_and_grid(TipAcc a, TipAcc *partials,
-                                                   unsigned *counter, TipAcc *lds,
-                                                   Finish finish) {
+// Block reduction of one TipAcc per wave (blockDim = 64 * nwaves <= 1024):
+// the block's total is written to partials[blockIdx.x].  `lds` needs room for
+// 16 TipAcc.  No grid-wide fence or counter: a second launch (tip_combine)
+// combines the partials, the kernel boundary ordering the two.
+__device__ __forceinline__ void tip_block_partial(TipAcc a, TipAcc *partials, TipAcc *lds) {
   tip_wave_reduce(a);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw = (blockDim.x + 63) >> 6;
   if (lane == 0) lds[wave] = a;
   __syncthreads();
-  __shared__ bool last;
   if (threadIdx.x == 0) {
     TipAcc b = lds[0];
     for (int w = 1; w < nw; ++w) tip_merge(b, lds[w].y, lds[w].idx, lds[w].fs, lds[w].bad);
     partials[blockIdx.x] = b;
-    __threadfence();
-    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-    last = (prev == gridDim.x - 1);
   }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
+}
+
+// One block combines n partials in a fixed order (lanes hold strided partial
+// sums, then the butterfly and the waves in order: deterministic for a given
+// n) and returns the total in thread 0.  `lds` needs room for 16 TipAcc.
+__device__ __forceinline__ TipAcc tip_combine(const TipAcc *partials, int n, TipAcc *lds) {
   TipAcc c;
   tip_init(c);
-  for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x) {
+  for (int b = threadIdx.x; b < n; b += blockDim.x) {
     TipAcc p = partials[b];
     tip_merge(c, p.y, p.idx, p.fs, p.bad);
   }
-  // deterministic combine: lanes hold strided partial sums in fixed order
   tip_wave_reduce(c);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
   if (lane == 0) lds[wave] = c;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    TipAcc t = lds[0];
-    for (int w = 1; w < nw; ++w) tip_merge(t, lds[w].y, lds[w].idx, lds[w].fs, lds[w].bad);
-    finish(t);
-    *counter = 0u;  // ready for the next launch
-  }
+  TipAcc t = lds[0];
+  for (int w = 1; w < nw; ++w) tip_merge(t, lds[w].y, lds[w].idx, lds[w].fs, lds[w].bad);
+  return t;
 }
 
 }  // namespace pf

@@ -34,10 +34,10 @@ struct alignas(16) TipResult {
 
 struct TipAcc;  // per-block partial (pf_device.hpp)
 
-// Workspace pieces shared by every kernel of a solver.
+// Workspace pieces of the reduction: one partial per workgroup and the
+// result record.
 struct Reduce {
   TipAcc *partials;
-  unsigned *counter;
   TipResult *result;
 };
 
@@ -158,6 +158,10 @@ enum At2D : int {
   kAtApproxTwoPoint = 3,  // approximated current, two-point <10> faces
   kAtDiffusionOnly = 4,   // psi held, U by D~ div[(1 - phi) grad U] alone (shells)
 };
+
+// Record msg as the calling thread's last error (pf_last_error) and return
+// code.
+int report_error(int code, const char *msg);
 
 template <typename T>
 hipError_t launch_step2d(const Step2DArgs<T> &a, const Geom2D &g, bool frozen, bool reduce,

@@ -17,8 +17,10 @@
 // are ordered strip-fastest, so consecutive waves read adjacent 256-byte row
 // pieces; the grid holds up to kMaxReduceBlocks workgroups of 4 waves and
 // strides over the runs.  Per-wave FP64 partials are combined by wave
-// shuffles, per workgroup, then by the last workgroup to finish, in
-// workgroup order (deterministic for a given lattice).
+// shuffles and per workgroup, then in workgroup order by a second,
+// one-workgroup launch (deterministic for a given lattice; no grid-wide fence
+// and arrival counter, whose device-scope fences cost far more on this device
+// than the extra launch).
 #include "pf_device.hpp"
 
 namespace pf {
@@ -96,14 +98,21 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs<T> a) {
     }
   }
   __shared__ TipAcc lds[16];
-  TipResult *res = a.red.result;
-  tip_block_and_grid(acc, a.red.partials, a.red.counter, lds, [res](const TipAcc &t) {
+  tip_block_partial(acc, a.red.partials, lds);
+}
+
+// The grid's partials in block order -> the result record.
+__global__ __launch_bounds__(256) void reduce_finish_kernel(Reduce red, int nblocks) {
+  __shared__ TipAcc lds[16];
+  const TipAcc t = tip_combine(red.partials, nblocks, lds);
+  if (threadIdx.x == 0) {
+    TipResult *res = red.result;
     res->y = t.y;
     res->idx = t.idx;
     res->fs_sum = t.fs;
     res->bad = t.bad;
     res->found = t.y > -__builtin_inf() ? 1 : 0;
-  });
+  }
 }
 
 }  // namespace
@@ -129,6 +138,9 @@ hipError_t launch_reduce(const ReduceArgs<T> &a, hipStream_t st) {
   ReduceArgs<T> b = a;
   b.rows = g.rows;
   hipLaunchKernelGGL((reduce_kernel<T>), dim3(g.blocks), dim3(256), 0, st, b);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(reduce_finish_kernel, dim3(1), dim3(256), 0, st, b.red, g.blocks);
   return hipGetLastError();
 }
 
