@@ -212,6 +212,26 @@ int pf_read_fields(pf_solver *s, double *phi, double *U, double *psi, int8_t *gr
  * lattice or dt exceeds pf_stable_dt's limit with that F1. */
 int pf_tip_state(pf_solver *s, pf_tip *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * reduction of pf_tip_state on caller-held device fields, with no solver.
+ * psi and U are device arrays of nx*ny*nz values (float for PF_F32, double
+ * for PF_F64), x fastest; pending = 1 reads them as owing one downward frame
+ * shift (as pf_device_fields / pf_frame_state report), else 0.  Fills the
+ * tip (found, index, x, y_frame, z; y_lab = y_frame), solid_fraction and
+ * nonfinite of *out; step, t, velocity and frame_shift are 0.  Runs on
+ * `stream` (NULL: the null stream) of the current device and waits for it.
+ * Its partials and result live in a fixed array of this library on
+ * each device (about 132 KB, held until the process ends), so it never
+ * allocates device memory; every call on one device shares that array, so
+ * calls that overlap on one device (several streams or host threads) race.
+ * Any lattice the library accepts fits (x-y and y-z planes below 2^30
+ * cells, at most 4e9 cells; ny >= 2): PF_ERR_ARG beyond that or for NULL
+ * pointers, PF_ERR_NONFINITE (with *out filled) when a value is NaN or Inf,
+ * PF_ERR_DEVICE when a HIP call fails. */
+int pf_tip_fields(const void *psi, const void *U, int32_t precision, int32_t nx, int32_t ny,
+                  int32_t nz, double h, int32_t pending, void *stream, pf_tip *out);
+
 /* Device pointers of the current psi and U arrays (element type per
  * precision, nx*ny*nz each, frame rows possibly pending one shift: see
  * pf_frame_state).  Valid until the next pf_step. */

@@ -34,7 +34,8 @@ PF_AT_APPROX, PF_AT_FULL = 0, 1
 PF_DIV_SHELLS, PF_DIV_TWO_POINT = 0, 1
 
 EXPORTED = ("pf_version", "pf_last_error", "pf_stable_dt", "pf_workspace_bytes", "pf_create",
-            "pf_step", "pf_step_diffusion", "pf_synchronize", "pf_read_fields", "pf_tip_state", "pf_device_fields",
+            "pf_step", "pf_step_diffusion", "pf_synchronize", "pf_read_fields", "pf_tip_state",
+            "pf_tip_fields", "pf_device_fields",
             "pf_frame_state", "pf_tune", "pf_autotune", "pf_geometry", "pf_destroy", "pf_batch_create",
             "pf_batch_step", "pf_batch_use_graph", "pf_batch_autotune", "pf_batch_destroy")
 
@@ -95,6 +96,8 @@ def load(path: str = LIB_PATH):
     lib.pf_read_fields.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double), P(C.c_double),
                                    P(C.c_int8)]
     lib.pf_tip_state.argtypes = [C.c_void_p, P(pf_tip)]
+    lib.pf_tip_fields.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                  C.c_int32, C.c_double, C.c_int32, C.c_void_p, P(pf_tip)]
     lib.pf_device_fields.argtypes = [C.c_void_p, P(C.c_void_p), P(C.c_void_p)]
     lib.pf_frame_state.argtypes = [C.c_void_p, P(C.c_int64), P(C.c_int32)]
     lib.pf_tune.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
@@ -109,6 +112,7 @@ def load(path: str = LIB_PATH):
     lib.pf_batch_destroy.argtypes = [C.c_void_p]
     lib.pf_batch_destroy.restype = None
     for name in ("pf_create", "pf_step", "pf_synchronize", "pf_read_fields", "pf_tip_state",
+                 "pf_tip_fields",
                  "pf_device_fields", "pf_frame_state", "pf_tune", "pf_autotune",
                  "pf_geometry", "pf_batch_create", "pf_batch_step", "pf_batch_use_graph", "pf_batch_autotune"):
         getattr(lib, name).restype = C.c_int
@@ -213,6 +217,21 @@ class Solver:
     def tip_state(self, allow_nonfinite: bool = False) -> dict:
         t = pf_tip()
         rc = load().pf_tip_state(self.handle, C.byref(t))
+        if rc != PF_OK and not (allow_nonfinite and rc == PF_ERR_NONFINITE):
+            _check(rc)
+        return {f: getattr(t, f) for f, _ in pf_tip._fields_}
+
+    def tip_fields(self, allow_nonfinite: bool = False) -> dict:
+        """pf_tip_fields on this solver's current device fields (the reduction
+        without allocation; no solver bookkeeping such as step or velocity)."""
+        psi, U = self.device_fields()
+        _, pend = self.frame_state()
+        t = pf_tip()
+        rc = load().pf_tip_fields(C.c_void_p(psi), C.c_void_p(U), self.precision,
+                                  self.params.nx, self.params.ny,
+                                  self.params.nz if self.params.dim == 3 else 1,
+                                  self.params.h, pend, C.c_void_p(self.stream.cuda_stream),
+                                  C.byref(t))
         if rc != PF_OK and not (allow_nonfinite and rc == PF_ERR_NONFINITE):
             _check(rc)
         return {f: getattr(t, f) for f, _ in pf_tip._fields_}
