@@ -60,36 +60,38 @@ int default_seg2d(int nx, int ny, int precision, int ncu) {
 // Batched members keep segments of at least 8 rows: the batch fills the chip
 // by itself.
 constexpr int kMinSegBatch2D = 8;
-// Default 3D geometry.  FP32: 14 z rows per workgroup (16 waves, the most
-// one workgroup holds: one workgroup per CU at the kernel's ~110 VGPRs, ring
-// waves costing 16/14 instead of 8/6 for two 6-row workgroups), with 32-row
-// segments when that gives at least 400 workgroups, else 16-row ones when
-// that gives 200, else 8.  FP64: 2 z rows (4 waves, the thread limit of its
-// launch bounds) and the longest of 32, 16, 8 rows that keeps 400
-// workgroups.  From a sweep of cubes 96^3..512^3 (one run each), this is
-// within 14-18% of the best tile on 96^3 and 160^3 and within 7% elsewhere
-// (128^3: 28.3 G cell-updates/s with (16, 14) against 19.9 with (16, 6);
-// 256^3: 42.2 with (32, 14) against 39.5 with (32, 6)); pf_autotune refines
+constexpr size_t kMaxLds3DBytes = 163840;  // LDS one gfx950 workgroup may allocate
+constexpr size_t kMaxLds3D = kMaxLds3DBytes;
+// Default 3D geometry.  z rows per wide workgroup: 14 in FP32 (16 waves, the
+// most one workgroup holds: one workgroup per CU at the kernel's 100-128
+// VGPRs, ring rows costing 16/14), 2 in FP64 (4 waves, its launch bound).
+// Segments: the count that minimises the estimated time rounds x (rows + 2.5),
+// where rounds = ceil(workgroups / resident workgroups) and a segment's
+// prologue costs about 2.5 rows; the rows of a column are split evenly.  On
+// 256^3 FP32 (4 wide strips and a thin one, 82 tile columns) that is 3
+// segments of 85-86 rows, 246 workgroups in one round; pf_autotune refines
 // it per lattice.
-std::pair<int, int> default_geom3d(const pf_params *p) {
-  auto blocks = [&](int seg, int zt) { return geom3d(p->nx, p->ny, p->nz, seg, zt).blocks; };
+std::pair<int, int> default_geom3d(const pf_params *p, int ncu) {
   const bool f64 = p->precision == PF_F64;
-  const int zt = std::min(f64 ? 2 : 14, std::max(1, p->nz));  // no idle z waves on thin lattices
-  int seg = 8;
-  if (f64) {
-    for (int s : {32, 16})
-      if (blocks(s, zt) >= 400) {
-        seg = s;
-        break;
-      }
-  } else if (blocks(32, zt) >= 400) {
-    seg = 32;
-  } else if (blocks(16, zt) >= 200) {
-    seg = 16;
+  const int zt = std::min(f64 ? 2 : 14, std::max(1, p->nz));
+  const int nw = zt + 2;
+  const size_t lds = step3d_lds_bytes(p->nx, zt, f64 ? 8 : 4);
+  const int by_waves = std::max(1, (f64 ? 8 : 16) / nw);
+  const int by_lds = std::max(1, (int)(kMaxLds3DBytes / lds));
+  const long long resident = (long long)std::max(1, ncu) * std::min(by_waves, by_lds);
+  int best = p->ny;
+  double best_cost = 1e300;
+  for (int n = 1; n <= std::max(1, p->ny / 4); ++n) {
+    const int rows = (p->ny + n - 1) / n;
+    const long long blocks = geom3d(p->nx, p->ny, p->nz, rows, zt).blocks;
+    const double cost = (double)((blocks + resident - 1) / resident) * (rows + 2.5);
+    if (cost < best_cost - 1e-9) {
+      best_cost = cost;
+      best = rows;
+    }
   }
-  return {seg, zt};
+  return {best, zt};
 }
-constexpr size_t kMaxLds3D = 163840;  // LDS one gfx950 workgroup may allocate
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -132,11 +134,6 @@ double stable_dt_for(const pf_params *p, double f1) {
   return p->h * p->h / (2.0 * p->dim * std::max(p->D, 1.0 / f1));
 }
 
-int max_step_blocks(const pf_params *p, int seg, int ztile) {
-  if (p->dim == 2) return geom2d(p->nx, p->ny, seg).blocks;
-  return geom3d(p->nx, p->ny, p->nz, seg, ztile).blocks;
-}
-
 struct Layout {
   size_t psi[2], U[2], grain, grain2, rot, frame[3], partials, result, total;
 };
@@ -152,10 +149,8 @@ Layout layout_of(const pf_params *p) {
   L.grain2 = o; o += align256(p->dynamic_grains ? n : 1);  // the next level's map
   L.rot = o; o += align256((size_t)(p->n_grains > 0 ? p->n_grains : 1) * 9 * es);
   for (int i = 0; i < 3; ++i) { L.frame[i] = o; o += 256; }
-  // per-block partials: enough for the finest segmentation the step accepts
-  // (2D: one row per segment; 3D: 4 rows)
-  int nb = std::max(max_step_blocks(p, p->dim == 2 ? 1 : 4, 1),
-                    reduce_blocks(p->nx, p->ny, p->dim == 3 ? p->nz : 1));
+  // one partial per workgroup of the reduction
+  int nb = reduce_blocks(p->nx, p->ny, p->dim == 3 ? p->nz : 1);
   L.partials = o; o += align256((size_t)(nb + 64) * tip_acc_bytes());
   L.result = o; o += 256;
   L.total = o;
@@ -432,6 +427,10 @@ int step_impl(pf_solver *s, long long nsteps, bool diffusion_only = false) {
     a.bcx = p.bc[0]; a.bcy = p.bc[1]; a.bcz = p.bc[2];
     a.wout = g.wout; a.nstrips = g.nstrips; a.nzt = g.nzt; a.nsegs = g.nsegs; a.seg = g.seg;
     a.ztile = g.ztile;
+    a.segbase = g.segbase; a.segrem = g.segrem;
+    a.ncols = g.ncols; a.ncols_wide = g.ncols_wide;
+    a.thin_g = g.thin_g; a.thin_G = g.thin_G; a.thin_wout = g.thin_wout;
+    a.thin_nzt = g.thin_nzt; a.thin_segbase = g.thin_segbase; a.thin_segrem = g.thin_segrem;
     a.c = c;
     a.hd = p.h; a.y0 = p.y0; a.Vp = p.Vp; a.dtd = s->dt;
     a.frame = p.frame; a.shift_row = p.shift_row;
@@ -703,12 +702,22 @@ int autotune_impl(pf_solver *s, int steps) {
       add(-k, s->ztile);
     }
   } else {
+    // rows per segment, each candidate kept only when it gives a segment
+    // count not listed yet for its z rows (the rows are split evenly)
     const int zmax = s->p.precision == PF_F64 ? 2 : 14;
-    for (int zt : {1, 2, 4, 5, 6, 8, 10, 12, 14})
-      for (int seg : {8, 16, 32, 64})
-        if (zt <= zmax && zt <= s->p.nz && seg <= std::max(8, s->p.ny) &&
-            step3d_lds_bytes(zt, sizeof(T)) <= kMaxLds3D)
-          add(seg, zt);
+    for (int zt : {1, 2, 4, 6, 8, 10, 12, 14}) {
+      std::vector<int> seen;
+      if (zt == s->ztile) seen.push_back(geom3d(s->p.nx, s->p.ny, s->p.nz, s->seg, zt).nsegs);
+      for (int seg : {8, 12, 16, 24, 32, 43, 64, 86, 128, 256}) {
+        if (zt > zmax || zt > s->p.nz || seg > std::max(8, s->p.ny) ||
+            step3d_lds_bytes(s->p.nx, zt, sizeof(T)) > kMaxLds3D)
+          continue;
+        const int ns = geom3d(s->p.nx, s->p.ny, s->p.nz, seg, zt).nsegs;
+        if (std::find(seen.begin(), seen.end(), ns) != seen.end()) continue;
+        seen.push_back(ns);
+        add(seg, zt);
+      }
+    }
   }
   const int k = pick_fastest((int)cand.size(), [&](int i) {
     t.seg = cand[i].first;
@@ -965,7 +974,7 @@ int pf_create(const pf_params *p, const pf_init *init, void *workspace, size_t w
     s->seg = default_seg2d(p->nx, p->ny, p->precision, s->ncu);
     s->ztile = 1;
   } else {
-    std::tie(s->seg, s->ztile) = default_geom3d(p);
+    std::tie(s->seg, s->ztile) = default_geom3d(p, s->ncu);
   }
   if (r2 == PF_OK)
     r2 = p->precision == PF_F64 ? upload<double>(s, init) : upload<float>(s, init);
@@ -1121,7 +1130,7 @@ int pf_tune(pf_solver *s, int32_t rows_per_segment, int32_t z_tile) {
   if (s->p.dim == 3 && s->p.precision == PF_F64 && z_tile > 2)
     return fail(PF_ERR_ARG, "FP64 3D workgroups hold at most 2 z rows (4 waves)");
   if (s->p.dim == 3 &&
-      step3d_lds_bytes(z_tile, s->p.precision == PF_F64 ? 8 : 4) > kMaxLds3D)
+      step3d_lds_bytes(s->p.nx, z_tile, s->p.precision == PF_F64 ? 8 : 4) > kMaxLds3D)
     return fail(PF_ERR_ARG, "z_tile too large for the LDS of one workgroup at this precision");
   s->seg = rows_per_segment;
   if (s->p.dim == 3) s->ztile = z_tile;

@@ -106,6 +106,10 @@ struct Step3DArgs {
   T R[9];                // single grain
   int nx, ny, nz, bcx, bcy, bcz;
   int wout, nstrips, nzt, nsegs, seg, ztile;
+  int segbase, segrem;          // rows of a segment: segbase, one more for the first segrem
+  int ncols, ncols_wide;        // tile columns (strip, z tile), wide ones first
+  int thin_g, thin_G, thin_wout;  // thin strip: lane groups per wave, lanes per group, width
+  int thin_nzt, thin_segbase, thin_segrem;  // its z tiles and segments
   Coef<T> c;
   double hd, y0, Vp, dtd;
   long long step;
@@ -134,11 +138,19 @@ struct Geom2D {
 };
 Geom2D geom2d(int nx, int ny, int seg, int ncu = 0);
 
+// Launch geometry of the 3D step: nstrips strips of wout output columns
+// (wide tiles, one z row per wave) and, when nx mod 60 columns remain and
+// at least two lane groups of that width fit a wave, a thin strip of
+// thin_g groups of thin_G lanes per wave (thin_nzt z tiles); ztile z rows per
+// wide workgroup of ztile + 2 waves; each column's ny rows split evenly
+// between nsegs segments of at most seg rows (thin columns: thin_nsegs).
 struct Geom3D {
-  int wout, nstrips, ztile, nzt, nsegs, seg, blocks, threads;
+  int wout, nstrips, ztile, nzt, nsegs, seg, segbase, segrem, blocks, threads;
+  int thin_g, thin_G, thin_wout, thin_nzt, ncols_wide, ncols;
+  int thin_nsegs, thin_segbase, thin_segrem;
 };
 Geom3D geom3d(int nx, int ny, int nz, int seg, int ztile);
-size_t step3d_lds_bytes(int ztile, size_t elem);
+size_t step3d_lds_bytes(int nx, int ztile, size_t elem);
 
 size_t tip_acc_bytes();
 // Launch geometry of the reduction: rows per column walk and workgroups

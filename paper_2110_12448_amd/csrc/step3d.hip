@@ -115,46 +115,67 @@ struct Diff9 {
 template <typename T>
 constexpr int max_threads3d() { return sizeof(T) == 8 ? 256 : 1024; }
 
-template <typename T, bool kFrozen, bool kReduce, bool kMulti, bool kShell3>
-__global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T> a) {
+// One tile of the step: a workgroup of nw waves marching up one y segment.
+// Wide tiles (kWide): each wave is one z row of 64 lanes holding a strip of
+// up to 60 output columns with a 2-column halo on each side.  Thin tiles
+// hold the strip of the last nx mod 60 columns: each wave is g lane groups
+// of G = width + 4 lanes, each group its own z row, so that a narrow strip
+// does not leave most lanes idle; the tile then spans g times as many z rows.
+// In both, the lowest and highest z rows of the tile are ring rows whose
+// results only feed their neighbours.  Lane moves (DPP) cross group
+// boundaries only in halo lanes, whose results are never used; lanes past the
+// last group repeat its last lane.  Returns the lane's moving-frame vote.
+template <typename T, bool kFrozen, bool kReduce, bool kMulti, bool kShell3, bool kWide>
+__device__ __forceinline__ bool step3d_tile(const Step3DArgs<T> &a, int strip, int zt, int segi,
+                                            unsigned char *smem_raw) {
   using M = Math<T>;
   const Coef<T> &c = a.c;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   T *sm = reinterpret_cast<T *>(smem_raw);
-  const int Z = a.ztile, NZR = Z + 4, NW = Z + 2;
-  const int SLOT = NZR * kRS;
+  const int nwv = (int)(blockDim.x >> 6);
+  const int GL = kWide ? 64 : a.thin_G;   // lanes per group
+  const int g = kWide ? 1 : a.thin_g;     // groups (z rows) per wave
+  const int RS = kWide ? kRS : GL + 2;    // LDS row stride: lane l at l + 1, pads at 0 and GL + 1
+  const int NW = nwv * g;                 // z rows of the tile, ring rows included
+  const int Z = NW - 2, NZR = Z + 4;
+  const int SLOT = NZR * RS;
   // Field rings, 5 row slots of NZR z layers, stored [slot][layer][field][lane]
   // so that the four fields of one (row, layer) sit at fixed offsets from one
   // another and share one address computation.
-  T *XL = sm + 4 * 5 * SLOT;  // link exchange [row parity][to above, to below][wave][lane]
-  T *FZ = XL + 4 * NW * 64;  // z-up face flux of each wave's row [wave][lane]
-  int8_t *gL = reinterpret_cast<int8_t *>(FZ + NW * 64);  // grains, 5 row slots
+  T *XL = sm + 4 * 5 * SLOT;  // link exchange [row parity][to above, to below][z row][lane]
+  T *FZ = XL + 4 * NW * GL;   // z-up face flux of each z row [z row][lane]
+  int8_t *gL = reinterpret_cast<int8_t *>(FZ + NW * GL);  // grains, 5 row slots
 
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-  const int lb = xcd_remap3((int)blockIdx.x, (int)gridDim.x);
-  const int strip = lb % a.nstrips;
-  const int rest = lb / a.nstrips;
-  const int zt = rest % a.nzt;
-  const int segi = rest / a.nzt;
-
-  const int x = strip * a.wout - 2 + lane;
+  int grp = 0, lx = lane;
+  if (!kWide) {
+    grp = min(lane / GL, g - 1);
+    lx = min(lane - grp * GL, GL - 1);
+  }
+  const bool valid = kWide || lane < g * GL;
+  const int zr = kWide ? w : w * g + grp;  // z row within the tile
+  const int wout = kWide ? a.wout : a.thin_wout;
+  const int x = (kWide ? strip * a.wout : a.nstrips * a.wout) - 2 + lx;
   const int gx = ghost(x, nx, a.bcx);
-  const bool out_lane = lane >= 2 && lane < 2 + a.wout && x < nx;
+  const bool out_lane = valid && lx >= 2 && lx < 2 + wout && x < nx;
   const int z0 = zt * Z;
-  const int z = z0 - 1 + w;
-  const int zi = w + 1;
-  const bool out_wave = w >= 1 && w <= Z && z < nz;
-  const bool ring = (w == 0) || (w == Z + 1);
-  const int zh = (w == 0) ? z0 - 2 : z0 + Z + 1;
-  const int zih = (w == 0) ? 0 : Z + 3;
+  const int z = z0 - 1 + zr;
+  const int zi = zr + 1;
+  const bool out_wave = zr >= 1 && zr <= Z && z < nz;  // uniform over a wave in wide tiles
+  const bool ring = (zr == 0) || (zr == Z + 1);
+  const int zh = (zr == 0) ? z0 - 2 : z0 + Z + 1;
+  const int zih = (zr == 0) ? 0 : Z + 3;
   const size_t plane = (size_t)nx * (size_t)ny;
   const size_t pz = (size_t)ghost(z, nz, a.bcz) * plane + (size_t)gx;
   const size_t pzh = (size_t)ghost(zh, nz, a.bcz) * plane + (size_t)gx;
   const size_t pzd = (size_t)ghost(z - 1, nz, a.bcz) * plane + (size_t)gx;
-  const int y0 = segi * a.seg;
-  const int ye = min(y0 + a.seg, ny);
+  // the rows of a column are split evenly between its segments (thin
+  // columns have their own, shorter segments)
+  const int segbase = kWide ? a.segbase : a.thin_segbase;
+  const int segrem = kWide ? a.segrem : a.thin_segrem;
+  const int y0 = segi * segbase + min(segi, segrem);
+  const int ye = y0 + segbase + (segi < segrem ? 1 : 0);
 
   const int pend = a.frame ? a.frame_in->pending : 0;
   const long long shift = a.frame ? a.frame_in->base + pend : 0;
@@ -171,8 +192,13 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
     return (size_t)j * (size_t)nx;
   };
   auto slot5 = [](int r) { return (r + 10) % 5; };
-  // index of lane 0 of field f at row slot s, z layer zz
-  auto at = [&](int f, int s, int zz) -> int { return ((s * NZR + zz) * 4 + f) * kRS + lane + 1; };
+  // LDS index of field f at row slot s in z layer zi + dz, this lane's column:
+  // the lane's part of the index is computed once (thin tiles have a z row
+  // per lane group)
+  const int LAY = 4 * RS;              // elements per z layer of a slot
+  const int SLOTF = NZR * LAY;         // elements per row slot
+  const int zoc = zi * LAY + lx + 1;
+  auto at = [&](int f, int s, int dz) -> int { return s * SLOTF + f * RS + dz * LAY + zoc; };
   auto rot_of = [&](int g) -> Rot3<T> {
     Rot3<T> R;
     const T *q = kMulti ? a.rot + 9 * g : a.R;
@@ -181,7 +207,7 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
     return R;
   };
   // LDS element of field f at row slot s, z layer zz, lane offset dx
-  auto L = [&](int f, int s, int zz, int dx) -> T { return sm[at(f, s, zz) + dx]; };
+  auto L = [&](int f, int s, int dz, int dx) -> T { return sm[at(f, s, dz) + dx]; };
 
   // Divergence neighbourhoods: a z-row or y-row beyond a no-flux wall is read
   // as its mirror image (alpha_A included, which the ring waves cannot
@@ -195,6 +221,8 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
     return min(max(zz - z0 + 2, 0), NZR - 1);
   };
   const int zl[3] = {zlayer(z - 1), zlayer(z), zlayer(z + 1)};
+  const int zlo[3] = {zl[0] * LAY + lx + 1, zl[1] * LAY + lx + 1, zl[2] * LAY + lx + 1};
+  const int gzo = zi * RS + lx + 1;  // the same for the int8 grain ring (no field axis)
   auto yslot = [&](int j) {
     if (a.bcy == PF_BC_NOFLUX) {
       if (j < 0) j = -j - 1;
@@ -226,12 +254,12 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
   }
 
   // U of the waiting row qf from its own part and the neighbours' links
-  // (output waves only: their neighbours w - 1 and w + 1 exist in the tile)
+  // (output rows only: their neighbours zr - 1 and zr + 1 exist in the tile)
   auto finalize = [&](int qf) {
     if (!out_wave) return;
     const int par = qf & 1;
-    const T below = XL[((par * 2 + 0) * NW + (w - 1)) * 64 + lane];
-    const T above = XL[((par * 2 + 1) * NW + (w + 1)) * 64 + lane];
+    const T below = XL[((par * 2 + 0) * NW + (zr - 1)) * GL + lx];
+    const T above = XL[((par * 2 + 1) * NW + (zr + 1)) * GL + lx];
     store_row(a.U_out + (pz - (size_t)gx) + (size_t)qf * nx, nx, x, out_lane,
                waitU + c.dt * waitDen * (waitBase - below - above));
   };
@@ -254,12 +282,12 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
     fN = M::tanh_(pN * isq2);
     const int sN = slot5(r);
     {
-      const int o = at(kPsi, sN, zi);
+      const int o = at(kPsi, sN, 0);
       sm[o] = pN;
-      sm[o + (kU - kPsi) * kRS] = uN;
-      sm[o + (kAD - kPsi) * kRS] = c.D * (T(1) - fN);
-      if (kMulti) gL[(sN * NZR + zi) * kRS + lane + 1] = (int8_t)gN;
-      if (ring) sm[at(kPsi, sN, zih)] = hN;
+      sm[o + (kU - kPsi) * RS] = uN;
+      sm[o + (kAD - kPsi) * RS] = c.D * (T(1) - fN);
+      if (kMulti) gL[sN * NZR * RS + gzo] = (int8_t)gN;
+      if (ring) sm[sN * SLOTF + zih * LAY + lx + 1] = hN;
     }
     __syncthreads();
     if constexpr (P == 0) {
@@ -272,11 +300,11 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
     if constexpr (P == 1) {
       // only the y face between rows m and m+1 (lower cell (x, m, z)), in
       // the same form as the steady state's north face
-      const T cx0 = L(kPsi, s0, zi, 1) - L(kPsi, s0, zi, -1);
-      const T cx1 = L(kPsi, sp1, zi, 1) - L(kPsi, sp1, zi, -1);
-      const T cz0 = L(kPsi, s0, zi + 1, 0) - L(kPsi, s0, zi - 1, 0);
-      const T cz1 = L(kPsi, sp1, zi + 1, 0) - L(kPsi, sp1, zi - 1, 0);
-      FyS = aniso3<T, 1>(cx0 + cx1, T(4) * (L(kPsi, sp1, zi, 0) - L(kPsi, s0, zi, 0)), cz0 + cz1,
+      const T cx0 = L(kPsi, s0, 0, 1) - L(kPsi, s0, 0, -1);
+      const T cx1 = L(kPsi, sp1, 0, 1) - L(kPsi, sp1, 0, -1);
+      const T cz0 = L(kPsi, s0, 1, 0) - L(kPsi, s0, -1, 0);
+      const T cz1 = L(kPsi, sp1, 1, 0) - L(kPsi, sp1, -1, 0);
+      FyS = aniso3<T, 1>(cx0 + cx1, T(4) * (L(kPsi, sp1, 0, 0) - L(kPsi, s0, 0, 0)), cz0 + cz1,
                          rot_of(gC), c, c.f3_eps);
       __syncthreads();
       return;
@@ -291,7 +319,7 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
 #pragma unroll
           for (int dx = -1; dx <= 1; ++dx) {
             if (!kShell3 && dx != 0 && dy != 0 && dz != 0) continue;  // corners unused
-            Pn[nb(dx, dy, dz)] = L(kPsi, sy[dy + 1], zi + dz, dx);
+            Pn[nb(dx, dy, dz)] = L(kPsi, sy[dy + 1], dz, dx);
           }
       const T p0 = Pn[nb(0, 0, 0)];
       T s1 = T(0), s2 = T(0), s3 = T(0);
@@ -342,7 +370,7 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
       T FzU = aniso3<T, 2>(cx + (Pn[nb(1, 0, 1)] - Pn[nb(-1, 0, 1)]),
                            cy + (Pn[nb(0, 1, 1)] - Pn[nb(0, -1, 1)]),
                            T(4) * (Pn[nb(0, 0, 1)] - p0), R, c, c.f3_eps);
-      FZ[w * 64 + lane] = FzU;
+      FZ[zr * GL + lx] = FzU;
       T FzD;
       if (w == 0) {
         Rot3<T> Rd = R;
@@ -352,7 +380,7 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
                            T(4) * (p0 - Pn[nb(0, 0, -1)]), Rd, c, c.f3_eps);
       }
       __syncthreads();
-      if (w != 0) FzD = FZ[(w - 1) * 64 + lane];
+      if (zr != 0) FzD = FZ[(zr - 1) * GL + lx];
       const T ac2 = ac * ac;
       // the standard Laplacian of the remainder is the <100> sum s1 / h^2
       T Nn = (FxE - FxW + FyN - FyS + FzU - FzD) * c.f3_scale - ac2 * (s1 * c.cStd);
@@ -372,7 +400,7 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
         T fr = from_right(aA), fl = from_left(aA);
         aA = (x == -1) ? fr : ((x == nx) ? fl : aA);
       }
-      sm[at(kAA, s0, zi)] = aA;
+      sm[at(kAA, s0, 0)] = aA;
       aAq = aAm;
       aAm = aA;
       // dynamic grains: the grain of row m at the next level (a liquid cell,
@@ -396,8 +424,8 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
             take(Pn[nb(1, 0, 0)], gE);
             take(Pn[nb(0, -1, 0)], gS);
             take(Pn[nb(0, 1, 0)], gN);
-            take(Pn[nb(0, 0, -1)], (int)gL[(s0 * NZR + zi - 1) * kRS + lane + 1]);
-            take(Pn[nb(0, 0, 1)], (int)gL[(s0 * NZR + zi + 1) * kRS + lane + 1]);
+            take(Pn[nb(0, 0, -1)], (int)gL[s0 * NZR * RS + gzo - RS]);
+            take(Pn[nb(0, 0, 1)], (int)gL[s0 * NZR * RS + gzo + RS]);
           }
           if (out_wave && out_lane)
             a.grain_out[pz + (size_t)m * nx - (size_t)gx + (size_t)x] = (int8_t)gn;
@@ -420,7 +448,7 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
       const int q = m - 1;
       const int sl[3] = {yslot(q - 1), yslot(q), yslot(q + 1)};
       auto rd = [&](int f, int dy, int dz, int dx) -> T {
-        return sm[at(f, sl[dy + 1], zl[dz + 1]) + dx];
+        return sm[sl[dy + 1] * SLOTF + f * RS + zlo[dz + 1] + dx];
       };
       constexpr bool kFull = P == 4;
       auto abars = [&](int AL, T Pyq) -> Abar9<T> {
@@ -530,8 +558,8 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
         const T fWU = bD.WU * dU.WU + bA.WU * dP.WU;
         // links the waves above and below take with the opposite sign
         const int par = q & 1;
-        XL[((par * 2 + 0) * NW + w) * 64 + lane] = fUp + from_left(fEU) + from_right(fWU) + NUprev;
-        XL[((par * 2 + 1) * NW + w) * 64 + lane] = NDprev;
+        XL[((par * 2 + 0) * NW + zr) * GL + lx] = fUp + from_left(fEU) + from_right(fWU) + NUprev;
+        XL[((par * 2 + 1) * NW + zr) * GL + lx] = NDprev;
         T own = ((fE + fN_) + (fUp + fNE)) + ((fNW + fEU) + (fWU + fNU)) + fND + f111;
         T part = own - from_left(fE) - southSum;
         // finish the row below with its neighbours' links (published one
@@ -569,8 +597,31 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
         over |= crossing_reaches(f0, f1, ms, a.shift_row, ythr, a.hd);
     }
   }
+  return over;
+}
+
+template <typename T, bool kFrozen, bool kReduce, bool kMulti, bool kShell3>
+__global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  // wide tiles first, segment by segment (strip fastest, then z tile), then
+  // the thin strip's tiles likewise
+  const int lb = xcd_remap3((int)blockIdx.x, (int)gridDim.x);
+  const int nwide = a.ncols_wide * a.nsegs;
+  bool over;
+  if (lb < nwide) {
+    const int segi = lb / a.ncols_wide;
+    const int col = lb - segi * a.ncols_wide;
+    over = step3d_tile<T, kFrozen, kReduce, kMulti, kShell3, true>(a, col % a.nstrips,
+                                                                   col / a.nstrips, segi, smem_raw);
+  } else {
+    const int t = lb - nwide;
+    const int segi = t / a.thin_nzt;
+    over = step3d_tile<T, kFrozen, kReduce, kMulti, kShell3, false>(a, 0, t - segi * a.thin_nzt,
+                                                                    segi, smem_raw);
+  }
   if (kReduce) {
-    const bool any = __any(over && out_wave);
+    const bool any = __any(over);
+    const int lane = threadIdx.x & 63;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       const FrameState fi = *a.frame_in;
       a.frame_out->base = fi.base + fi.pending;
@@ -585,23 +636,64 @@ __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T
 
 Geom3D geom3d(int nx, int ny, int nz, int seg, int ztile) {
   Geom3D g;
-  g.nstrips = (nx + 59) / 60;
-  g.wout = (nx + g.nstrips - 1) / g.nstrips;
   g.ztile = ztile < 1 ? 1 : (ztile > 14 ? 14 : ztile);
+  const int nw = g.ztile + 2;
+  // strips of 60 output columns; the last nx mod 60 columns form a thin
+  // strip of lane groups when two or more groups of width + 4 lanes fit a
+  // wave (at most 4), else the strips share the columns evenly
+  const int nfull = nx / 60, r = nx - 60 * nfull;
+  const int gr = r > 0 ? (64 / (r + 4) < 4 ? 64 / (r + 4) : 4) : 0;
+  g.thin_g = 0;
+  g.thin_G = 0;
+  g.thin_wout = 0;
+  g.thin_nzt = 0;
+  if (r == 0 || gr >= 2) {
+    g.nstrips = nfull;
+    g.wout = 60;
+    if (r > 0) {
+      g.thin_g = gr;
+      g.thin_G = r + 4;
+      g.thin_wout = r;
+      const int zt_thin = nw * gr - 2;
+      g.thin_nzt = (nz + zt_thin - 1) / zt_thin;
+    }
+  } else {
+    g.nstrips = (nx + 59) / 60;
+    g.wout = (nx + g.nstrips - 1) / g.nstrips;
+  }
   g.nzt = (nz + g.ztile - 1) / g.ztile;
+  g.ncols_wide = g.nstrips * g.nzt;
+  g.ncols = g.ncols_wide + g.thin_nzt;
   g.seg = seg < 1 ? 1 : seg;
   g.nsegs = (ny + g.seg - 1) / g.seg;
-  g.threads = 64 * (g.ztile + 2);
-  g.blocks = g.nstrips * g.nzt * g.nsegs;
+  g.segbase = ny / g.nsegs;
+  g.segrem = ny - g.segbase * g.nsegs;
+  // a thin tile's row costs about 9% more than a wide one's (its LDS
+  // addresses are per lane), so its segments are 11/12 as long
+  const int seg_thin = g.seg * 11 / 12 < 1 ? 1 : g.seg * 11 / 12;
+  g.thin_nsegs = g.thin_nzt > 0 ? (ny + seg_thin - 1) / seg_thin : 0;
+  g.thin_segbase = g.thin_nsegs > 0 ? ny / g.thin_nsegs : 0;
+  g.thin_segrem = g.thin_nsegs > 0 ? ny - g.thin_segbase * g.thin_nsegs : 0;
+  g.threads = 64 * nw;
+  g.blocks = g.ncols_wide * g.nsegs + g.thin_nzt * g.thin_nsegs;
   return g;
 }
 
-size_t step3d_lds_bytes(int ztile, size_t elem) {
-  // four 5-row rings of (ztile + 4) z layers, the link exchange, the z-face
-  // fluxes, and a 5-row int8 ring of grains
-  return ((size_t)20 * (size_t)(ztile + 4) * (size_t)kRS + (size_t)5 * (size_t)(ztile + 2) * 64) *
-             elem +
-         (((size_t)5 * (size_t)(ztile + 4) * (size_t)kRS + 15) & ~(size_t)15);
+size_t step3d_lds_bytes(int nx, int ztile, size_t elem) {
+  // four 5-row rings of (z rows + 2) z layers, the link exchange, the z-face
+  // fluxes, and a 5-row int8 ring of grains; the larger of a wide tile's
+  // and a thin tile's
+  const Geom3D g = geom3d(nx, 8, 8, 8, ztile);
+  const size_t nw = (size_t)g.ztile + 2;
+  size_t wide = ((size_t)20 * (nw + 2) * (size_t)kRS + (size_t)5 * nw * 64) * elem +
+                (((size_t)5 * (nw + 2) * (size_t)kRS + 15) & ~(size_t)15);
+  size_t thin = 0;
+  if (g.thin_g > 0) {
+    const size_t NW = nw * (size_t)g.thin_g, RS = (size_t)g.thin_G + 2;
+    thin = ((size_t)20 * (NW + 2) * RS + (size_t)5 * NW * (size_t)g.thin_G) * elem +
+           (((size_t)5 * (NW + 2) * RS + 15) & ~(size_t)15);
+  }
+  return wide > thin ? wide : thin;
 }
 
 // Launch one instantiation; workgroups above 64 KB of LDS need the kernel's
@@ -632,7 +724,7 @@ template <typename T>
 hipError_t launch_step3d(const Step3DArgs<T> &a, const Geom3D &g, bool frozen, bool reduce,
                          bool multi, hipStream_t st) {
   dim3 grid(g.blocks), block(g.threads);
-  size_t lds = step3d_lds_bytes(g.ztile, sizeof(T));
+  size_t lds = step3d_lds_bytes(a.nx, g.ztile, sizeof(T));
   const bool shell3 = a.c.cD3 != T(0) || a.c.cL3 != T(0) || a.c.cG3 != T(0);
   hipError_t e = hipSuccess;
 #define PF_L3(F, R, MU, S3) e = launch3<T, F, R, MU, S3>(a, grid, block, lds, st)

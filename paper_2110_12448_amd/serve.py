@@ -70,14 +70,36 @@ def _batchable(prob: dict) -> bool:
     return prob["dim"] == 2 and not prob.get("antitrapping", 0) and not prob.get("two_point", 0)
 
 
+def _geom3d_blocks(nx: int, ny: int, nz: int, seg: int, ztile: int) -> int:
+    """Workgroups of one 3D step launch (the library's tile layout: strips of
+    60 columns, the nx mod 60 remainder as a thin strip of lane groups when
+    two or more groups of width + 4 lanes fit a wave (at most 4), z tiles of
+    ztile rows (thin: (ztile + 2) * groups - 2), segments of at most seg rows,
+    11/12 of that in the thin strip)."""
+    nw = ztile + 2
+    nfull, r = nx // 60, nx % 60
+    gr = min(4, 64 // (r + 4)) if r > 0 else 0
+    thin_nzt = 0
+    if r == 0 or gr >= 2:
+        nstrips = nfull
+        if r > 0:
+            thin_nzt = -(-nz // (nw * gr - 2))
+    else:
+        nstrips = -(-nx // 60)
+    nsegs = -(-ny // seg)
+    seg_thin = max(1, seg * 11 // 12)
+    thin_nsegs = -(-ny // seg_thin) if thin_nzt else 0
+    return nstrips * -(-nz // ztile) * nsegs + thin_nzt * thin_nsegs
+
+
 def estimated_waves(prob: dict, batched: bool = False, cus: int = 256) -> int:
     """Waves one step launch of this solve occupies at the library's default
     FP32 geometry on a device of `cus` compute units: the measure of how much
     of the chip a solve fills.  60 output columns per wave; in 2D k =
     round(R^0.4) waves per SIMD with R = strips * ny / SIMDs, at most one
     segment per row, and inside a batch segments of that length but at least
-    8 rows; 3D workgroups of 14 z rows in 16 waves, on segments of 32 rows
-    when that gives 400 workgroups, else 16 rows when that gives 200, else 8."""
+    8 rows; in 3D workgroups of 14 z rows in 16 waves (one per CU), with the
+    segment count that minimises rounds x (rows + 2.5)."""
     strips = -(-prob["nx"] // 60)
     if prob["dim"] == 2:
         ny, simds = prob["ny"], 4 * cus
@@ -86,11 +108,16 @@ def estimated_waves(prob: dict, batched: bool = False, cus: int = 256) -> int:
         if batched:
             nsegs = -(-ny // max(8, -(-ny // nsegs)))
         return strips * nsegs
-    zt = min(14, prob["nz"])
-    tiles = -(-prob["nz"] // zt)
-    blocks = {s: strips * -(-prob["ny"] // s) * tiles for s in (32, 16, 8)}
-    seg = 32 if blocks[32] >= 400 else (16 if blocks[16] >= 200 else 8)
-    return blocks[seg] * (zt + 2)
+    nx, ny, nz = prob["nx"], prob["ny"], prob["nz"]
+    zt = min(14, nz)
+    best, best_cost = ny, None
+    for n in range(1, max(1, ny // 4) + 1):
+        rows = -(-ny // n)
+        blocks = _geom3d_blocks(nx, ny, nz, rows, zt)
+        cost = -(-blocks // cus) * (rows + 2.5)
+        if best_cost is None or cost < best_cost - 1e-9:
+            best, best_cost = rows, cost
+    return _geom3d_blocks(nx, ny, nz, best, zt) * (zt + 2)
 
 
 def _work(r: Request) -> int:

@@ -54,7 +54,7 @@ def test_autotune_keeps_state_and_results(case):
     if dim == 2:
         assert -64 <= seg <= -1 and zt == 1      # waves per SIMD
     else:
-        assert 8 <= seg <= 64 and 1 <= zt <= (2 if prec == 1 else 14)
+        assert 4 <= seg <= 256 and 1 <= zt <= (2 if prec == 1 else 14)
     s.tune(seg, zt)                      # the choice is accepted as a manual setting
     s.step(after)
     assert _same(_state(s), want)

@@ -177,14 +177,19 @@ def test_tip_golden_3d_10k():
 
 
 @pytest.mark.parametrize("w", [wl.ISO_3D, wl.ISO_3D_441])
-def test_tiles_do_not_change_results_fp32(w):
-    """Bitwise identical fields for every launch geometry."""
-    pr = _poly(40, ny=36, n_grains=4, seed_radius=10.0)
+@pytest.mark.parametrize("n", [40, 76, 64])
+def test_tiles_do_not_change_results_fp32(w, n):
+    """Bitwise identical fields for every launch geometry.  n = 40: one strip
+    of 40 columns; 76: a strip of 60 and a thin strip of 16 columns in 3 lane
+    groups per wave; 64: a strip of 60 and a thin strip of 4 in 4 groups."""
+    pr = _poly(n, ny=36, n_grains=4, seed_radius=10.0)
     pr["w"] = tuple(w)
     ref = run_gpu(pr, 0, 12, tune=(16, 6))
-    for tune in ((4, 1), (8, 3), (32, 8), (12, 5), (16, 14), (8, 11), (24, 10)):
+    for tune in ((4, 1), (8, 3), (32, 8), (12, 5), (16, 14), (8, 11), (24, 10), (36, 14)):
         out = run_gpu(pr, 0, 12, tune=tune)
         assert np.array_equal(out[2], ref[2]) and np.array_equal(out[1], ref[1]), tune
+    ophi, oU, _, st, p = run_oracle(pr, 12)
+    assert max(_cmp(ref[0], ophi), _cmp(ref[1], oU)) <= TOL_F32
 
 
 def test_polycrystal_full_size_fp32():
