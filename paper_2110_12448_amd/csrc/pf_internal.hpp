@@ -139,11 +139,11 @@ struct Geom2D {
 Geom2D geom2d(int nx, int ny, int seg, int ncu = 0);
 
 // Launch geometry of the 3D step: nstrips strips of wout output columns
-// (wide tiles, one z row per wave) and, when nx mod 60 columns remain and
-// at least two lane groups of that width fit a wave, a thin strip of
-// thin_g groups of thin_G lanes per wave (thin_nzt z tiles); ztile z rows per
-// wide workgroup of ztile + 2 waves; each column's ny rows split evenly
-// between nsegs segments of at most seg rows (thin columns: thin_nsegs).
+// (wide tiles, one z row per wave) and, when at most 17 of nx mod 60 columns
+// remain, a thin strip of thin_g = 3 or 4 groups of thin_G = 21 or 16 lanes
+// per wave (thin_nzt z tiles); ztile z rows per wide workgroup of ztile + 2
+// waves; each column's ny rows split evenly between nsegs segments of at
+// most seg rows (thin columns: thin_nsegs of at most 3/4 of that).
 struct Geom3D {
   int wout, nstrips, ztile, nzt, nsegs, seg, segbase, segrem, blocks, threads;
   int thin_g, thin_G, thin_wout, thin_nzt, ncols_wide, ncols;

@@ -116,25 +116,31 @@ template <typename T>
 constexpr int max_threads3d() { return sizeof(T) == 8 ? 256 : 1024; }
 
 // One tile of the step: a workgroup of nw waves marching up one y segment.
-// Wide tiles (kWide): each wave is one z row of 64 lanes holding a strip of
+// Wide tiles (kG = 1): each wave is one z row of 64 lanes holding a strip of
 // up to 60 output columns with a 2-column halo on each side.  Thin tiles
-// hold the strip of the last nx mod 60 columns: each wave is g lane groups
-// of G = width + 4 lanes, each group its own z row, so that a narrow strip
-// does not leave most lanes idle; the tile then spans g times as many z rows.
+// hold the strip of the last nx mod 60 columns: each wave is kG = 3 or 4 lane
+// groups of 21 or 16 lanes, each group its own z row, so that a narrow strip
+// does not leave most lanes idle; the tile then spans kG times as many z rows.
+// The group width is a compile-time constant, so LDS offsets other than the
+// lane's own part fold into the instructions' immediate offsets.
 // In both, the lowest and highest z rows of the tile are ring rows whose
 // results only feed their neighbours.  Lane moves (DPP) cross group
 // boundaries only in halo lanes, whose results are never used; lanes past the
 // last group repeat its last lane.  Returns the lane's moving-frame vote.
-template <typename T, bool kFrozen, bool kReduce, bool kMulti, bool kShell3, bool kWide>
+template <int kG>
+constexpr int group_lanes() { return kG == 1 ? 64 : (kG == 3 ? 21 : 16); }
+
+template <typename T, bool kFrozen, bool kReduce, bool kMulti, bool kShell3, int kG>
 __device__ __forceinline__ bool step3d_tile(const Step3DArgs<T> &a, int strip, int zt, int segi,
                                             unsigned char *smem_raw) {
   using M = Math<T>;
   const Coef<T> &c = a.c;
   T *sm = reinterpret_cast<T *>(smem_raw);
   const int nwv = (int)(blockDim.x >> 6);
-  const int GL = kWide ? 64 : a.thin_G;   // lanes per group
-  const int g = kWide ? 1 : a.thin_g;     // groups (z rows) per wave
-  const int RS = kWide ? kRS : GL + 2;    // LDS row stride: lane l at l + 1, pads at 0 and GL + 1
+  constexpr bool kWide = kG == 1;
+  constexpr int GL = group_lanes<kG>();   // lanes per group
+  constexpr int g = kG;                   // groups (z rows) per wave
+  constexpr int RS = GL + 2;              // LDS row stride: lane l at l + 1, pads at 0 and GL + 1
   const int NW = nwv * g;                 // z rows of the tile, ring rows included
   const int Z = NW - 2, NZR = Z + 4;
   const int SLOT = NZR * RS;
@@ -603,21 +609,25 @@ __device__ __forceinline__ bool step3d_tile(const Step3DArgs<T> &a, int strip, i
 template <typename T, bool kFrozen, bool kReduce, bool kMulti, bool kShell3>
 __global__ __launch_bounds__(max_threads3d<T>()) void step3d_kernel(Step3DArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  // wide tiles first, segment by segment (strip fastest, then z tile), then
-  // the thin strip's tiles likewise
+  // Wide tiles first, segment by segment (strip fastest, then z tile), then
+  // the thin strip's tiles likewise (thin tiles have their own, shorter
+  // segments: their rows cost more)
   const int lb = xcd_remap3((int)blockIdx.x, (int)gridDim.x);
   const int nwide = a.ncols_wide * a.nsegs;
   bool over;
   if (lb < nwide) {
     const int segi = lb / a.ncols_wide;
     const int col = lb - segi * a.ncols_wide;
-    over = step3d_tile<T, kFrozen, kReduce, kMulti, kShell3, true>(a, col % a.nstrips,
-                                                                   col / a.nstrips, segi, smem_raw);
+    over = step3d_tile<T, kFrozen, kReduce, kMulti, kShell3, 1>(a, col % a.nstrips,
+                                                               col / a.nstrips, segi, smem_raw);
   } else {
     const int t = lb - nwide;
     const int segi = t / a.thin_nzt;
-    over = step3d_tile<T, kFrozen, kReduce, kMulti, kShell3, false>(a, 0, t - segi * a.thin_nzt,
-                                                                    segi, smem_raw);
+    const int zt = t - segi * a.thin_nzt;
+    if (a.thin_g == 3)
+      over = step3d_tile<T, kFrozen, kReduce, kMulti, kShell3, 3>(a, 0, zt, segi, smem_raw);
+    else
+      over = step3d_tile<T, kFrozen, kReduce, kMulti, kShell3, 4>(a, 0, zt, segi, smem_raw);
   }
   if (kReduce) {
     const bool any = __any(over);
@@ -639,20 +649,21 @@ Geom3D geom3d(int nx, int ny, int nz, int seg, int ztile) {
   g.ztile = ztile < 1 ? 1 : (ztile > 14 ? 14 : ztile);
   const int nw = g.ztile + 2;
   // strips of 60 output columns; the last nx mod 60 columns form a thin
-  // strip of lane groups when two or more groups of width + 4 lanes fit a
-  // wave (at most 4), else the strips share the columns evenly
+  // strip of lane groups when three (21 lanes, up to 17 columns) or four (16
+  // lanes, up to 12 columns) groups fit a wave, else the strips share the
+  // columns evenly
   const int nfull = nx / 60, r = nx - 60 * nfull;
-  const int gr = r > 0 ? (64 / (r + 4) < 4 ? 64 / (r + 4) : 4) : 0;
+  const int gr = r == 0 ? 0 : (r <= 12 ? 4 : (r <= 17 ? 3 : 1));
   g.thin_g = 0;
   g.thin_G = 0;
   g.thin_wout = 0;
   g.thin_nzt = 0;
-  if (r == 0 || gr >= 2) {
+  if (r == 0 || gr >= 3) {
     g.nstrips = nfull;
     g.wout = 60;
     if (r > 0) {
       g.thin_g = gr;
-      g.thin_G = r + 4;
+      g.thin_G = gr == 3 ? 21 : 16;
       g.thin_wout = r;
       const int zt_thin = nw * gr - 2;
       g.thin_nzt = (nz + zt_thin - 1) / zt_thin;
@@ -668,9 +679,10 @@ Geom3D geom3d(int nx, int ny, int nz, int seg, int ztile) {
   g.nsegs = (ny + g.seg - 1) / g.seg;
   g.segbase = ny / g.nsegs;
   g.segrem = ny - g.segbase * g.nsegs;
-  // a thin tile's row costs about 9% more than a wide one's (its LDS
-  // addresses are per lane), so its segments are 11/12 as long
-  const int seg_thin = g.seg * 11 / 12 < 1 ? 1 : g.seg * 11 / 12;
+  // a thin tile's row costs more than a wide one's (its LDS addresses have a
+  // per-lane part and its three or four z rows share each wave), so its
+  // segments are 3/4 as long
+  const int seg_thin = g.seg * 3 / 4 < 1 ? 1 : g.seg * 3 / 4;
   g.thin_nsegs = g.thin_nzt > 0 ? (ny + seg_thin - 1) / seg_thin : 0;
   g.thin_segbase = g.thin_nsegs > 0 ? ny / g.thin_nsegs : 0;
   g.thin_segrem = g.thin_nsegs > 0 ? ny - g.thin_segbase * g.thin_nsegs : 0;

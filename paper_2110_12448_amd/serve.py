@@ -72,24 +72,22 @@ def _batchable(prob: dict) -> bool:
 
 def _geom3d_blocks(nx: int, ny: int, nz: int, seg: int, ztile: int) -> int:
     """Workgroups of one 3D step launch (the library's tile layout: strips of
-    60 columns, the nx mod 60 remainder as a thin strip of lane groups when
-    two or more groups of width + 4 lanes fit a wave (at most 4), z tiles of
-    ztile rows (thin: (ztile + 2) * groups - 2), segments of at most seg rows,
-    11/12 of that in the thin strip)."""
+    60 columns, the nx mod 60 remainder as a thin strip of 3 lane groups (13
+    to 17 columns) or 4 (up to 12) with (ztile + 2) * groups - 2 z rows per
+    tile, z tiles of ztile rows, segments of at most seg rows, 3/4 of that in
+    the thin strip)."""
     nw = ztile + 2
     nfull, r = nx // 60, nx % 60
-    gr = min(4, 64 // (r + 4)) if r > 0 else 0
+    gr = 0 if r == 0 else (4 if r <= 12 else (3 if r <= 17 else 1))
     thin_nzt = 0
-    if r == 0 or gr >= 2:
+    if r == 0 or gr >= 3:
         nstrips = nfull
         if r > 0:
             thin_nzt = -(-nz // (nw * gr - 2))
     else:
         nstrips = -(-nx // 60)
-    nsegs = -(-ny // seg)
-    seg_thin = max(1, seg * 11 // 12)
-    thin_nsegs = -(-ny // seg_thin) if thin_nzt else 0
-    return nstrips * -(-nz // ztile) * nsegs + thin_nzt * thin_nsegs
+    thin_nsegs = -(-ny // max(1, seg * 3 // 4)) if thin_nzt else 0
+    return nstrips * -(-nz // ztile) * -(-ny // seg) + thin_nzt * thin_nsegs
 
 
 def estimated_waves(prob: dict, batched: bool = False, cus: int = 256) -> int:

@@ -29,11 +29,12 @@ def test_trace_is_seeded_and_mixed():
     ((256, 256), True, 5 * 32),                  # batched: 60-column strips x 8-row segments
     ((1024, 1024), True, 18 * 128),
     ((2048, 2048), True, 35 * 137),              # longer alone (146 segments): 15 rows
-    # 3D: 14 z rows in 16 waves; 2 strips of 60 and a thin one (4 groups of
-    # 12 lanes, 62 z rows per tile) with 11 and 12 segments: 256 workgroups
-    ((128, 128, 128), False, (2 * 10 * 11 + 3 * 12) * 16),
-    # 4 strips of 60 and a thin one (3 groups of 20 lanes, 46 z rows per tile)
-    # with 3 and 4 segments: 252 workgroups in one round
+    # 3D: 14 z rows in 16 waves; 2 strips of 60 in 10 segments of 13 rows
+    # and a thin strip (4 groups of 16 lanes, 62 z rows per tile) in 15
+    # segments of at most 9: 245 workgroups in one round
+    ((128, 128, 128), False, (2 * 10 * 10 + 3 * 15) * 16),
+    # 4 strips of 60 in 3 segments and a thin one (3 groups of 21 lanes, 46
+    # z rows per tile) in 4: 252 workgroups in one round
     ((256, 256, 256), False, (4 * 19 * 3 + 6 * 4) * 16),
 ])
 def test_estimated_waves(shape, batched, want):
