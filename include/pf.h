@@ -260,12 +260,14 @@ int pf_tune(pf_solver *s, int32_t rows_per_segment, int32_t z_tile);
 int pf_geometry(pf_solver *s, int32_t *rows_per_segment, int32_t *z_tile);
 
 /* Tile autotuner: time each candidate launch geometry (2D: 1..32 waves per
- * SIMD, as pf_tune's -k; 3D: rows per segment 8..64 times z rows per workgroup, within the
+ * SIMD, as pf_tune's -k; 3D: rows per segment 8..256 times z rows per workgroup, within the
  * LDS of one workgroup and at most 2 z rows in FP64) over steps_per_trial
  * steps (after 2 warm-up steps) with HIP events on the solver's stream, two
  * interleaved passes keeping each candidate's better time, and keep the
  * fastest as if set by pf_tune; the geometry in use stays unless another is
- * more than 3% faster (near-equal candidates do not flip with noise).  Trials run on a scratch device copy
+ * more than 3% faster there and, re-timed against it in three interleaved
+ * passes of 4 x steps_per_trial steps, still more than 2% faster (near-equal
+ * candidates do not flip with noise).  Trials run on a scratch device copy
  * of the workspace (one extra workspace allocated and freed here), so the
  * solve itself neither advances nor changes; results never depend on the
  * choice.  Synchronises.  seg and ztile (either may be NULL) receive the
@@ -308,7 +310,7 @@ int pf_batch_use_graph(pf_batch *b, int32_t steps_per_graph);
  * own segment length, at least 8 rows; for a member whose geometry asks for
  * waves per SIMD, the longest segment that gives alone) over
  * steps_per_trial steps on scratch copies of all
- * member workspaces, with the same two passes and 3% rule as pf_autotune,
+ * member workspaces, with the same passes and margins as pf_autotune,
  * then rebuild the batch with the choice (kept until the batch is destroyed;
  * it overrides the members' own pf_tune settings inside the batch only).  The
  * members do not advance.  Synchronises.  *seg (may be NULL) receives the

@@ -641,25 +641,35 @@ double time_steps(hipStream_t st, int steps, F run) {
   return out;
 }
 
-// Index of the fastest of n candidates timed by trial(i) (seconds, negative on
-// failure; -1 returned then).  Candidate 0 is the geometry in use: each
-// candidate is timed in two interleaved passes and keeps its better time,
-// and another candidate replaces candidate 0 only when it is more than 3%
-// faster, so that timing noise between near-equal geometries does not flip
-// the choice from run to run.
+// Index of the fastest of n candidates timed by trial(i, m) (seconds of m
+// times the trial's base step count, negative on failure; -1 returned then).
+// Candidate 0 is the geometry in use: each candidate is timed in two
+// interleaved passes and keeps its better time.  A candidate more than 3%
+// faster than candidate 0 is then confirmed against it in three interleaved
+// passes four times as long, and replaces it only when it is still more than
+// 2% faster there: a short trial can misjudge near-equal geometries, and the
+// choice should not flip from run to run on timing noise.
 template <typename F>
 int pick_fastest(int n, F trial) {
   std::vector<double> best(n, 1e300);
   for (int pass = 0; pass < 2; ++pass)
     for (int i = 0; i < n; ++i) {
-      double sec = trial(i);
+      double sec = trial(i, 1);
       if (sec < 0.0) return -1;
       best[i] = std::min(best[i], sec);
     }
   int k = 0;
   for (int i = 1; i < n; ++i)
     if (best[i] < best[k]) k = i;
-  return best[k] < 0.97 * best[0] ? k : 0;
+  if (!(best[k] < 0.97 * best[0])) return 0;
+  double b0 = 1e300, bk = 1e300;
+  for (int pass = 0; pass < 3; ++pass) {
+    const double s0 = trial(0, 4), sk = trial(k, 4);
+    if (s0 < 0.0 || sk < 0.0) return -1;
+    b0 = std::min(b0, s0);
+    bk = std::min(bk, sk);
+  }
+  return bk < 0.98 * b0 ? k : 0;
 }
 
 // A copy of solver s whose workspace is a fresh device copy of s's (the
@@ -719,10 +729,10 @@ int autotune_impl(pf_solver *s, int steps) {
       }
     }
   }
-  const int k = pick_fastest((int)cand.size(), [&](int i) {
+  const int k = pick_fastest((int)cand.size(), [&](int i, int m) {
     t.seg = cand[i].first;
     t.ztile = cand[i].second;
-    return time_steps(s->stream, steps, [&](int n) { return step_impl<T>(&t, n); });
+    return time_steps(s->stream, steps * m, [&](int n) { return step_impl<T>(&t, n); });
   });
   (void)hipStreamSynchronize(s->stream);
   (void)hipFree(t.ws);
@@ -761,10 +771,10 @@ int batch_autotune_impl(pf_batch *b, int steps) {
     if (seg != b->seg_fixed) cand.push_back(seg);
   int bseg = b->seg_fixed;
   if (rc == PF_OK) {
-    const int k = pick_fastest((int)cand.size(), [&](int i) {
+    const int k = pick_fastest((int)cand.size(), [&](int i, int mult) {
       tb.seg_fixed = cand[i];
       tb.expect.assign(made, -1);  // rebuild with this segment length
-      return time_steps(b->stream, steps, [&](int m) { return batch_step<T>(&tb, m); });
+      return time_steps(b->stream, steps * mult, [&](int m) { return batch_step<T>(&tb, m); });
     });
     if (k < 0)
       rc = fail(PF_ERR_DEVICE, "batch autotune trial failed");
