@@ -688,8 +688,8 @@ def main():
     torch.cuda.synchronize()
     kern_ms = sum(a.elapsed_time(b) for a, b in evs) / n
     # the on-demand reduction (tip, solid fraction, finiteness): pf_tip_state
-    # enqueues one reduction kernel and two 32-byte copies on the solver's
-    # stream and waits; timed on that stream
+    # enqueues the two reduction launches and one 48-byte copy on the
+    # solver's stream and waits; timed on that stream
     tip = s.tip_state()
     nt = 20
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))

@@ -467,10 +467,10 @@ int reduce_impl(pf_solver *s, TipResult *res, FrameState *fr) {
   a.red = Reduce{reinterpret_cast<TipAcc *>(s->ws + s->L.partials),
                  reinterpret_cast<TipResult *>(s->ws + s->L.result)};
   PF_HIP(launch_reduce<T>(a, s->stream));
+  // the result record carries a copy of the frame record the reduction read
   PF_HIP(hipMemcpyAsync(res, a.red.result, sizeof(TipResult), hipMemcpyDeviceToHost, s->stream));
-  PF_HIP(hipMemcpyAsync(fr, s->ws + s->L.frame[s->fcur], sizeof(FrameState), hipMemcpyDeviceToHost,
-                        s->stream));
   PF_HIP(hipStreamSynchronize(s->stream));
+  *fr = res->frame;
   return PF_OK;
 }
 

@@ -14,6 +14,7 @@
 #include <string>
 
 #include "pf_device.hpp"
+#include "tip_device.hpp"
 #include "pf_internal.hpp"
 
 using namespace pf;

@@ -23,16 +23,20 @@ struct alignas(16) FrameState {
   int pad;
 };
 
-// Result of a grid-wide tip / solid-fraction / finiteness reduction.
+// Result of a grid-wide tip / solid-fraction / finiteness reduction, with a
+// copy of the frame record the reduction read (zero when it was given none;
+// written by the main pass, the rest by the combining launch), so that one
+// copy to the host returns both.
 struct alignas(16) TipResult {
   double y;          // crossing height in the frame, valid when found
   long long idx;     // linear frame index of the cell below the crossing
   double fs_sum;     // sum over cells of (1 + phi)/2
   unsigned bad;      // number of non-finite psi or U values
   int found;
+  FrameState frame;
 };
 
-struct TipAcc;  // per-block partial (pf_device.hpp)
+struct TipAcc;  // per-block partial (tip_device.hpp)
 
 // Workspace pieces of the reduction: one partial per workgroup and the
 // result record.
@@ -154,7 +158,7 @@ size_t step3d_lds_bytes(int nx, int ztile, size_t elem);
 
 size_t tip_acc_bytes();
 // Launch geometry of the reduction: rows per column walk and workgroups
-// (256 threads; at most kMaxReduceBlocks).
+// (at most kMaxReduceBlocks).
 constexpr int kMaxReduceBlocks = 4096;
 struct GeomReduce {
   int rows, blocks;

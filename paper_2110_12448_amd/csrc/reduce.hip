@@ -15,23 +15,32 @@
 // walk has no branch: per column the highest crossing row of the run is kept
 // by selects and its FP64 height formed once at the end of the run.  Runs
 // are ordered strip-fastest, so consecutive waves read adjacent 256-byte row
-// pieces; the grid holds up to kMaxReduceBlocks workgroups of 4 waves and
+// pieces; the grid holds up to kMaxReduceBlocks workgroups of kReduceWaves waves and
 // strides over the runs.  Per-wave FP64 partials are combined by wave
 // shuffles and per workgroup, then in workgroup order by a second,
 // one-workgroup launch (deterministic for a given lattice; no grid-wide fence
 // and arrival counter, whose device-scope fences cost far more on this device
 // than the extra launch).
 #include "pf_device.hpp"
+#include "tip_device.hpp"
 
 namespace pf {
 
 namespace {
 
+// waves per workgroup of the main pass (one partial per workgroup)
+constexpr int kReduceWaves = 4;
+// rows of a column walk whose loads are issued together
+constexpr int kChunk = 8;
+
 template <typename T>
-__global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs<T> a) {
+__global__ __launch_bounds__(64 * kReduceWaves) void reduce_kernel(ReduceArgs<T> a) {
   using M = Math<T>;
   const int nx = a.nx, ny = a.ny, nz = a.nz;
-  const int pend = a.frame ? a.frame->pending : a.pending;
+  // the frame record (its pending shift decides which stored row a frame
+  // row reads); workgroup 0 also copies it into the result record
+  const FrameState fr = a.frame ? *a.frame : FrameState{0, a.pending, 0};
+  const int pend = fr.pending;
   const int lane = threadIdx.x & 63;
   const int wpb = blockDim.x >> 6;
   const long long wave = (long long)blockIdx.x * wpb + (threadIdx.x >> 6);
@@ -57,30 +66,44 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs<T> a) {
     const size_t base = (size_t)l * plane + (size_t)(in ? x : nx - 1);
     const int y0 = seg * rows;
     const int ye = min(y0 + rows, ny);
-    T p = a.psi[base + srow(y0)];
-    T f = M::tanh_(p * isq2);
     // per column the highest crossing row wins: crossing heights lie in
-    // [j, j + 1) h, so a higher row is always further up; the loop keeps
+    // [j, j + 1) h, so a higher row is always further up; the walk keeps
     // that row and its two phi values with selects (no branch) and the FP64
-    // height is formed once per run
+    // height is formed once per run.  Rows go in chunks of kChunk whose loads
+    // are all issued before any is used (rows past the run reload its last
+    // row and are not counted).
     int bj = -1;
     T bf = T(0), bfn = T(0);
     double sf = 0.0;
     unsigned bad = 0u;
-#pragma unroll 4
-    for (int j = y0; j < ye; ++j) {
-      const T u = a.U[base + srow(j)];
-      const bool up = j + 1 < ny;
-      const T pn = a.psi[base + srow(up ? j + 1 : j)];
-      const T fn = M::tanh_(pn * isq2);
-      sf += (double)f;
-      bad += (M::finite(p) && M::finite(u)) ? 0u : 1u;
-      const bool cr = up && f >= T(0) && fn < T(0);
-      bj = cr ? j : bj;
-      bf = cr ? f : bf;
-      bfn = cr ? fn : bfn;
-      p = pn;
-      f = fn;
+    T p = a.psi[base + srow(y0)];
+    T f = T(0);  // phi of the first row: formed once the first chunk's loads are issued
+    for (int j0 = y0; j0 < ye; j0 += kChunk) {
+      T uv[kChunk], pv[kChunk];
+#pragma unroll
+      for (int k = 0; k < kChunk; ++k) {
+        const int j = min(j0 + k, ye - 1);
+        uv[k] = a.U[base + srow(j)];
+        pv[k] = a.psi[base + srow(min(j + 1, ny - 1))];
+      }
+      if (j0 == y0) f = M::tanh_(p * isq2);
+#pragma unroll
+      for (int k = 0; k < kChunk; ++k) {
+        const int j = j0 + k;
+        if (j < ye) {
+          const bool up = j + 1 < ny;
+          const T pn = pv[k];
+          const T fn = M::tanh_(pn * isq2);
+          sf += (double)f;
+          bad += (M::finite(p) && M::finite(uv[k])) ? 0u : 1u;
+          const bool cr = up && f >= T(0) && fn < T(0);
+          bj = cr ? j : bj;
+          bf = cr ? f : bf;
+          bfn = cr ? fn : bfn;
+          p = pn;
+          f = fn;
+        }
+      }
     }
     if (in) {
       // sum over the run of (1 + phi)/2
@@ -99,12 +122,18 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs<T> a) {
   }
   __shared__ TipAcc lds[16];
   tip_block_partial(acc, a.red.partials, lds);
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.red.result->frame = a.frame ? fr : FrameState{0, 0, 0};
 }
 
-// The grid's partials in block order -> the result record.
-__global__ __launch_bounds__(256) void reduce_finish_kernel(Reduce red, int nblocks) {
-  __shared__ TipAcc lds[16];
-  const TipAcc t = tip_combine(red.partials, nblocks, lds);
+// The grid's partials in block order -> the result record (one workgroup of
+// kFinishThreads; each thread holds at most kFinishPer partials).
+constexpr int kFinishThreads = 256;
+constexpr int kFinishPer = kMaxReduceBlocks / kFinishThreads;
+static_assert(kFinishPer * kFinishThreads >= kMaxReduceBlocks, "every partial has a thread");
+
+__global__ __launch_bounds__(kFinishThreads) void reduce_finish_kernel(Reduce red, int nblocks) {
+  __shared__ TipAcc lds[kFinishThreads / 64];
+  const TipAcc t = tip_combine<kFinishPer, kFinishThreads / 64>(red.partials, nblocks, lds);
   if (threadIdx.x == 0) {
     TipResult *res = red.result;
     res->y = t.y;
@@ -119,14 +148,17 @@ __global__ __launch_bounds__(256) void reduce_finish_kernel(Reduce red, int nblo
 
 size_t tip_acc_bytes() { return sizeof(TipAcc); }
 
-// Runs of 32 rows, halved (down to 4) until there are 8192 of them (8 waves
-// per SIMD on 256 CUs), so small lattices still spread over the chip.
+// Runs of 32 rows, halved (down to kMinRunRows) until there are kRunTarget of
+// them, so small lattices still spread over the chip.
+constexpr int kRunTarget = 4096;
+constexpr int kMinRunRows = 4;
+
 GeomReduce reduce_geometry(int nx, int ny, int nz) {
   const long long cols = (long long)((nx + 63) / 64) * nz;
   int rows = 32;
-  while (rows > 4 && cols * ((ny + rows - 1) / rows) < 8192) rows /= 2;
+  while (rows > kMinRunRows && cols * ((ny + rows - 1) / rows) < kRunTarget) rows /= 2;
   const long long items = cols * ((ny + rows - 1) / rows);
-  const long long blocks = (items + 3) / 4;
+  const long long blocks = (items + kReduceWaves - 1) / kReduceWaves;
   return GeomReduce{rows, (int)(blocks < kMaxReduceBlocks ? blocks : kMaxReduceBlocks)};
 }
 
@@ -137,10 +169,10 @@ hipError_t launch_reduce(const ReduceArgs<T> &a, hipStream_t st) {
   const GeomReduce g = reduce_geometry(a.nx, a.ny, a.nz);
   ReduceArgs<T> b = a;
   b.rows = g.rows;
-  hipLaunchKernelGGL((reduce_kernel<T>), dim3(g.blocks), dim3(256), 0, st, b);
+  hipLaunchKernelGGL((reduce_kernel<T>), dim3(g.blocks), dim3(64 * kReduceWaves), 0, st, b);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(reduce_finish_kernel, dim3(1), dim3(256), 0, st, b.red, g.blocks);
+  hipLaunchKernelGGL(reduce_finish_kernel, dim3(1), dim3(kFinishThreads), 0, st, b.red, g.blocks);
   return hipGetLastError();
 }
 

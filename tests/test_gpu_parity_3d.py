@@ -42,8 +42,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 @functools.lru_cache(maxsize=4)
-def _oracle_c3(n, nsteps):
-    pr = wl.config_polycrystal_3d(n=n)
+def _oracle_c3(n, nsteps, ny=None):
+    pr = wl.config_polycrystal_3d(n=n, ny=ny)
     p = oracle.Params.from_problem(pr)
     psi, U, st = oracle.step(p, pr["psi0"], pr["U0"], pr["grain"], nsteps)
     return pr, np.tanh(psi / SQ2), U, st, p
@@ -134,14 +134,17 @@ def test_moving_frame_3d(prec):
 
 @pytest.mark.parametrize("prec", [1, 0])
 def test_polycrystal_c3_recipe_100_steps(prec):
-    """The 256^3 polycrystal's recipe at 64^3 (8 Voronoi grains with uniform
-    random orientations, planar slab, frozen gradient, periodic x and z,
-    S-bar_{1,2,0}) for the 100 steps of the parity gate, in the benchmark's
-    launch geometry: 32-row segments of 14-row workgroups in FP32 (2 rows in
+    """The 256^3 polycrystal's recipe (8 Voronoi grains with uniform random
+    orientations, planar slab, frozen gradient, periodic x and z,
+    S-bar_{1,2,0}) for the 100 steps of the parity gate, on a 76 x 64 x 76
+    lattice tiled as the benchmark tiles 256^3 (86-row segments of 14-row
+    workgroups): strips of 60 columns plus a thin strip of 16 in three lane
+    groups of 21, three segments of 21-22 rows (the thin strip four shorter
+    ones), 14-row workgroups with a partial last z tile in FP32 (2 rows in
     FP64, the most its workgroups hold).  Every cell against the oracle, and
     the tip and solid fraction."""
-    pr, ophi, oU, st, p = _oracle_c3(64, 100)
-    tune = (32, 14) if prec == 0 else (32, 2)
+    pr, ophi, oU, st, p = _oracle_c3(76, 100, ny=64)
+    tune = (22, 14) if prec == 0 else (22, 2)
     phi, U, psi, tip, _ = run_gpu(pr, prec, 100, tune=tune)
     d = max(_cmp(phi, ophi), _cmp(U, oU))
     print("max diff %.3e" % d)
