@@ -272,7 +272,7 @@ int pf_geometry(pf_solver *s, int32_t *rows_per_segment, int32_t *z_tile);
  * solve itself neither advances nor changes; results never depend on the
  * choice.  Synchronises.  seg and ztile (either may be NULL) receive the
  * choice (ztile 1 in 2D).  PF_ERR_ARG for a NULL solver or steps_per_trial
- * < 1, PF_ERR_OOM when the scratch copy does not fit, PF_ERR_DEVICE when a
+ * outside [1, 2^20], PF_ERR_OOM when the scratch copy does not fit, PF_ERR_DEVICE when a
  * trial launch fails (the solve is then unchanged). */
 int pf_autotune(pf_solver *s, int32_t steps_per_trial, int32_t *seg, int32_t *ztile);
 
@@ -315,7 +315,7 @@ int pf_batch_use_graph(pf_batch *b, int32_t steps_per_graph);
  * it overrides the members' own pf_tune settings inside the batch only).  The
  * members do not advance.  Synchronises.  *seg (may be NULL) receives the
  * choice, 0 meaning each member's own segment length.  PF_ERR_ARG for a
- * NULL batch or steps_per_trial < 1, PF_ERR_OOM when the copies do not fit,
+ * NULL batch or steps_per_trial outside [1, 2^20], PF_ERR_OOM when the copies do not fit,
  * PF_ERR_DEVICE when a trial launch fails. */
 int pf_batch_autotune(pf_batch *b, int32_t steps_per_trial, int32_t *seg);
 

@@ -649,6 +649,10 @@ double time_steps(hipStream_t st, int steps, F run) {
 // passes four times as long, and replaces it only when it is still more than
 // 2% faster there: a short trial can misjudge near-equal geometries, and the
 // choice should not flip from run to run on timing noise.
+// Longest trial a caller may ask for: the confirming passes run four times as
+// many steps, which must stay within an int.
+constexpr int kMaxTrialSteps = 1 << 20;
+
 template <typename F>
 int pick_fastest(int n, F trial) {
   std::vector<double> best(n, 1e300);
@@ -875,7 +879,8 @@ void pf_batch_destroy(pf_batch *b) {
 
 int pf_autotune(pf_solver *s, int32_t steps_per_trial, int32_t *seg, int32_t *ztile) {
   if (!s) return fail(PF_ERR_ARG, "solver is NULL");
-  if (steps_per_trial < 1) return fail(PF_ERR_ARG, "steps_per_trial must be >= 1");
+  if (steps_per_trial < 1 || steps_per_trial > kMaxTrialSteps)
+    return fail(PF_ERR_ARG, "steps_per_trial must be in [1, 2^20]");
   int rc = s->p.precision == PF_F64 ? autotune_impl<double>(s, steps_per_trial)
                                     : autotune_impl<float>(s, steps_per_trial);
   if (rc != PF_OK) return rc;
@@ -886,7 +891,8 @@ int pf_autotune(pf_solver *s, int32_t steps_per_trial, int32_t *seg, int32_t *zt
 
 int pf_batch_autotune(pf_batch *b, int32_t steps_per_trial, int32_t *seg) {
   if (!b) return fail(PF_ERR_ARG, "batch is NULL");
-  if (steps_per_trial < 1) return fail(PF_ERR_ARG, "steps_per_trial must be >= 1");
+  if (steps_per_trial < 1 || steps_per_trial > kMaxTrialSteps)
+    return fail(PF_ERR_ARG, "steps_per_trial must be in [1, 2^20]");
   int rc = b->precision == PF_F64 ? batch_autotune_impl<double>(b, steps_per_trial)
                                   : batch_autotune_impl<float>(b, steps_per_trial);
   if (rc != PF_OK) return rc;

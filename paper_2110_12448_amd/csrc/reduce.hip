@@ -12,10 +12,11 @@
 // run of `rows` rows, loading psi and U once per cell and evaluating tanh
 // once per cell (phi of the row above is carried to the next row; a run
 // evaluates one extra row above its end for the last crossing test).  The
-// walk has no branch: per column the highest crossing row of the run is kept
-// by selects and its FP64 height formed once at the end of the run.  Runs
-// are ordered strip-fastest, so consecutive waves read adjacent 256-byte row
-// pieces; the grid holds up to kMaxReduceBlocks workgroups of kReduceWaves waves and
+// walk goes in chunks of kChunk rows whose loads are all issued before any
+// is used; per column the highest crossing row of the run is kept by selects
+// and its FP64 height formed once at the end of the run.  Runs are ordered
+// strip-fastest, so consecutive waves read adjacent 256-byte row pieces; the
+// grid holds up to kMaxReduceBlocks workgroups of kReduceWaves waves and
 // strides over the runs.  Per-wave FP64 partials are combined by wave
 // shuffles and per workgroup, then in workgroup order by a second,
 // one-workgroup launch (deterministic for a given lattice; no grid-wide fence
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(64 * kReduceWaves) void reduce_kernel(ReduceArgs<T>
       }
     }
   }
-  __shared__ TipAcc lds[16];
+  __shared__ TipAcc lds[kReduceWaves];
   tip_block_partial(acc, a.red.partials, lds);
   if (blockIdx.x == 0 && threadIdx.x == 0) a.red.result->frame = a.frame ? fr : FrameState{0, 0, 0};
 }

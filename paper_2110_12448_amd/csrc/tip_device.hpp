@@ -53,7 +53,7 @@ __device__ __forceinline__ void tip_wave_reduce(TipAcc &a) {
 
 // Block reduction of one TipAcc per wave (blockDim = 64 * nwaves <= 1024):
 // the block's total is written to partials[blockIdx.x].  `lds` needs room for
-// 16 TipAcc.  No grid-wide fence or counter: a second launch (tip_combine)
+// one TipAcc per wave.  No grid-wide fence or counter: a second launch (tip_combine)
 // combines the partials, the kernel boundary ordering the two.
 __device__ __forceinline__ void tip_block_partial(TipAcc a, TipAcc *partials, TipAcc *lds) {
   tip_wave_reduce(a);

@@ -64,9 +64,10 @@ def test_autotune_keeps_state_and_results(case):
 def test_autotune_rejects_bad_trial_count():
     pf = _pf()
     s = pf.Solver(wl.config_small_2d(0.0, n=32), precision=pf.PF_F32)
-    with pytest.raises(pf.PFError) as e:
-        s.autotune(0)
-    assert e.value.code == pf.PF_ERR_ARG
+    for bad in (0, (1 << 20) + 1):
+        with pytest.raises(pf.PFError) as e:
+            s.autotune(bad)
+        assert e.value.code == pf.PF_ERR_ARG
     s.close()
 
 
