@@ -196,8 +196,11 @@ int pf_synchronize(pf_solver *s);
 /* Synchronise and copy the state to host FP64 arrays of nx*ny*nz values in
  * frame coordinates (x fastest): phi = tanh(psi/sqrt2), the change of
  * variable of Sec. 2.1 (phi = +1 solid, -1 liquid), U, and psi itself.  Any
- * pointer may be NULL; grain (int8, the current map) likewise.  The caller
- * owns the arrays.  PF_ERR_DEVICE when a copy fails. */
+ * pointer may be NULL; grain (int8, the current map) likewise.  psi and U
+ * are copied in the field precision and widened, and phi is formed from the
+ * copied psi, on the host in FP64 (a conversion of the output only: the
+ * steps take their own phi on the device).  The caller owns the arrays.
+ * PF_ERR_DEVICE when a copy fails. */
 int pf_read_fields(pf_solver *s, double *phi, double *U, double *psi, int8_t *grain);
 
 /* Synchronise, reduce the current state on the device and fill *out: the
