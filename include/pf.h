@@ -248,7 +248,7 @@ int pf_frame_state(pf_solver *s, int64_t *shift, int32_t *pending);
  * 4..256; in 2D also -k for k = 1..64, asking for k waves per SIMD of the
  * device: each 60-column strip then takes as many segments as give k * 4 *
  * (compute units) waves in all, at most one per row, and the rows are split
- * evenly between them) and z rows per workgroup (3D, 1..14 in FP32, 1..2 in
+ * evenly between them) and z rows per workgroup (3D, 1..14 in FP32, 1..6 in
  * FP64, within the LDS of one workgroup; ignored in 2D).  Results do not
  * depend on it (only the work split changes); used by the tile autotuner.
  * PF_ERR_ARG outside these ranges. */
@@ -264,7 +264,7 @@ int pf_geometry(pf_solver *s, int32_t *rows_per_segment, int32_t *z_tile);
 
 /* Tile autotuner: time each candidate launch geometry (2D: 1..32 waves per
  * SIMD, as pf_tune's -k; 3D: rows per segment 8..256 times z rows per workgroup, within the
- * LDS of one workgroup and at most 2 z rows in FP64) over steps_per_trial
+ * LDS of one workgroup and at most 6 z rows in FP64) over steps_per_trial
  * steps (after 2 warm-up steps) with HIP events on the solver's stream, two
  * interleaved passes keeping each candidate's better time, and keep the
  * fastest as if set by pf_tune; the geometry in use stays unless another is

@@ -64,16 +64,17 @@ constexpr size_t kMaxLds3DBytes = 163840;  // LDS one gfx950 workgroup may alloc
 constexpr size_t kMaxLds3D = kMaxLds3DBytes;
 // Default 3D geometry.  z rows per wide workgroup: 14 in FP32 (16 waves, the
 // most one workgroup holds: one workgroup per CU at the kernel's 100-128
-// VGPRs, ring rows costing 16/14), 2 in FP64 (4 waves, its launch bound).
+// VGPRs, ring rows costing 16/14), 6 in FP64 (8 waves, its launch bound:
+// two waves per SIMD at its ~230 VGPRs, ring rows costing 8/6).
 // Segments: the count that minimises the estimated time rounds x (rows + 2.5),
 // where rounds = ceil(workgroups / resident workgroups) and a segment's
 // prologue costs about 2.5 rows; the rows of a column are split evenly.  On
-// 256^3 FP32 (4 wide strips and a thin one, 82 tile columns) that is 3
-// segments of 85-86 rows, 246 workgroups in one round; pf_autotune refines
-// it per lattice.
+// 256^3 FP32 (4 wide strips of 19 z tiles and a thin strip of 6) that is 3
+// segments of 85-86 rows (the thin strip 4 of 64), 252 workgroups in one
+// round; pf_autotune refines it per lattice.
 std::pair<int, int> default_geom3d(const pf_params *p, int ncu) {
   const bool f64 = p->precision == PF_F64;
-  const int zt = std::min(f64 ? 2 : 14, std::max(1, p->nz));
+  const int zt = std::min(f64 ? 6 : 14, std::max(1, p->nz));
   const int nw = zt + 2;
   const size_t lds = step3d_lds_bytes(p->nx, zt, f64 ? 8 : 4);
   const int by_waves = std::max(1, (f64 ? 8 : 16) / nw);
@@ -718,7 +719,7 @@ int autotune_impl(pf_solver *s, int steps) {
   } else {
     // rows per segment, each candidate kept only when it gives a segment
     // count not listed yet for its z rows (the rows are split evenly)
-    const int zmax = s->p.precision == PF_F64 ? 2 : 14;
+    const int zmax = s->p.precision == PF_F64 ? 6 : 14;
     for (int zt : {1, 2, 4, 6, 8, 10, 12, 14}) {
       std::vector<int> seen;
       if (zt == s->ztile) seen.push_back(geom3d(s->p.nx, s->p.ny, s->p.nz, s->seg, zt).nsegs);
@@ -1143,8 +1144,8 @@ int pf_tune(pf_solver *s, int32_t rows_per_segment, int32_t z_tile) {
                                           : "rows_per_segment must lie in [4, 256]");
   if (s->p.dim == 3 && (z_tile < 1 || z_tile > 14))
     return fail(PF_ERR_ARG, "z_tile must lie in [1, 14]");
-  if (s->p.dim == 3 && s->p.precision == PF_F64 && z_tile > 2)
-    return fail(PF_ERR_ARG, "FP64 3D workgroups hold at most 2 z rows (4 waves)");
+  if (s->p.dim == 3 && s->p.precision == PF_F64 && z_tile > 6)
+    return fail(PF_ERR_ARG, "FP64 3D workgroups hold at most 6 z rows (8 waves)");
   if (s->p.dim == 3 &&
       step3d_lds_bytes(s->p.nx, z_tile, s->p.precision == PF_F64 ? 8 : 4) > kMaxLds3D)
     return fail(PF_ERR_ARG, "z_tile too large for the LDS of one workgroup at this precision");

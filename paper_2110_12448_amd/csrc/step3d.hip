@@ -110,10 +110,10 @@ struct Diff9 {
 };
 
 // FP32 workgroups run up to 16 waves (ztile <= 14, at most 128 VGPRs per
-// lane); FP64 ones up to 4 (ztile <= 2), which leaves them the whole
-// register file.
+// lane); FP64 ones, which need about 230 VGPRs, up to 8 (ztile <= 6, two
+// waves per SIMD).
 template <typename T>
-constexpr int max_threads3d() { return sizeof(T) == 8 ? 256 : 1024; }
+constexpr int max_threads3d() { return sizeof(T) == 8 ? 512 : 1024; }
 
 // One tile of the step: a workgroup of nw waves marching up one y segment.
 // Wide tiles (kG = 1): each wave is one z row of 64 lanes holding a strip of

@@ -289,11 +289,14 @@ def test_tune_limits_3d():
     pf = _pf()
     pr = wl.problem(3, (16, 16, 16))
     s = pf.Solver(pr, precision=pf.PF_F64)
-    for seg, zt in ((8, 9), (8, 3), (300, 2), (-2, 2)):   # waves per SIMD: 2D only
+    # FP64 workgroups hold at most 6 z rows; waves per SIMD are 2D only
+    for seg, zt in ((8, 9), (8, 7), (300, 2), (-2, 2)):
         with pytest.raises(pf.PFError) as e:
             s.tune(seg, zt)
         assert e.value.code == pf.PF_ERR_ARG, (seg, zt)
-    s.tune(8, 2)
+    s.tune(8, 3)
+    s.tune(8, 6)
+    assert s.geometry() == (8, 6)
     s.close()
     s = pf.Solver(pr, precision=pf.PF_F32)
     for seg, zt in ((8, 15), (8, 0)):
