@@ -52,7 +52,7 @@ extern "C" {
 #define PF_F32 0
 #define PF_F64 1
 
-/* boundary condition per axis (Sec. 4.3.2, 6.2.2) */
+/* boundary condition per axis (no-flux: Sec. 4.3.2, 6.2.2; periodic: Sec. 4.3.3, 6.2.3) */
 #define PF_BC_NOFLUX 0           /* mirror about the boundary face */
 #define PF_BC_PERIODIC 1
 
@@ -75,7 +75,7 @@ extern "C" {
                                     cells and, for the full current, the face
                                     gradient from the normal difference and the
                                     four-point tangential difference: the standard
-                                    scheme S_{1,0} of Sec. 5 (with PF_SCHEME_STD) */
+                                    scheme S_{1,0} of Sec. 4.3.1 (with PF_SCHEME_STD) */
 
 typedef struct pf_params {
   int32_t dim;          /* 2 or 3 */

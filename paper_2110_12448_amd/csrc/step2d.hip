@@ -27,7 +27,7 @@
 // row (FP64 crossing heights, one flag per wave); with dynamic grains it
 // writes the next level's grain map.
 //
-// Variants (template kAT) for the scheme comparison of Sec. 5 (Table 1):
+// Variants (template kAT) for the scheme comparison of Sec. 4.3 (Table 1):
 //   kAtApproxShells    the approximated current on shell fluxes (S-bar_{2,1});
 //   kAtFullShells      the full current div[alpha grad psi/|grad psi|] of
 //                      Eq. Anti_convention: each shell flux of the A
