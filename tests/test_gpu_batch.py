@@ -136,3 +136,28 @@ def test_batch_large_members_frozen_frame_graph_vs_oracle(prec):
         prs.append(wl.problem(2, (nx, ny), alpha0_deg=a0, seed=300 + i, frame=1,
                               shift_row=12, seed_radius=14.0))
     check_batch(prs, prec, [("b", 60), ("s", 3, 2), ("b", 40)], graph=6)
+
+
+def test_batch_full_workload_autotuned_graph_vs_oracle():
+    """The batched workload itself (64 solves, sides 256..1024, 28 M cells, frozen
+    gradient) in the launch configuration the benchmark times: the segment
+    length pf_batch_autotune picks for the whole batch and 10-launch graph
+    epochs.  One replay and 3 eager steps, then every member against the
+    oracle (FP32 within 1e-5)."""
+    pf = _pf()
+    prs = wl.config_batched_2d()
+    ss = [pf.Solver(pr, precision=pf.PF_F32) for pr in prs]
+    b = pf.Batch(ss, graph_steps=10)
+    seg = b.autotune(5)
+    print("batched workload: %d solves, rows per segment %d" % (len(prs), seg), flush=True)
+    b.step(13)
+    worst = 0.0
+    for i, pr in enumerate(prs):
+        phi, U, _, _ = ss[i].read_fields()
+        fr = ss[i].frame_state()
+        worst = max(worst, against_oracle(pr, 0, 13, phi, U, fr[0]))
+        if i % 16 == 15:
+            print("members 0..%d checked, max diff %.2e" % (i, worst), flush=True)
+    b.close()
+    for s in ss:
+        s.close()
