@@ -642,6 +642,10 @@ double time_steps(hipStream_t st, int steps, F run) {
   return out;
 }
 
+// Longest trial a caller may ask for: the confirming passes run four times as
+// many steps, which must stay within an int.
+constexpr int kMaxTrialSteps = 1 << 20;
+
 // Index of the fastest of n candidates timed by trial(i, m) (seconds of m
 // times the trial's base step count, negative on failure; -1 returned then).
 // Candidate 0 is the geometry in use: each candidate is timed in two
@@ -650,10 +654,6 @@ double time_steps(hipStream_t st, int steps, F run) {
 // passes four times as long, and replaces it only when it is still more than
 // 2% faster there: a short trial can misjudge near-equal geometries, and the
 // choice should not flip from run to run on timing noise.
-// Longest trial a caller may ask for: the confirming passes run four times as
-// many steps, which must stay within an int.
-constexpr int kMaxTrialSteps = 1 << 20;
-
 template <typename F>
 int pick_fastest(int n, F trial) {
   std::vector<double> best(n, 1e300);
