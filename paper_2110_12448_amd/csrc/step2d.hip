@@ -116,6 +116,12 @@ constexpr int kMinWaves2D =
             (kAT == kAtApproxShells || kAT == kAtApproxTwoPoint || kAT == kAtDiffusionOnly)
         ? 3
         : 1;
+// The batched kernel's FP32 variants hold 4 waves per SIMD: unconstrained,
+// its frozen variants settle at 124-132 VGPRs, where the 4th wave comes and
+// goes with small changes to the body; held to 128, two spill a register or
+// two outside the row loop.
+template <typename T, bool kMulti>
+constexpr int kMinWavesBatch2D = sizeof(T) == 4 ? 4 : kMinWaves2D<T, kMulti, kAtApproxShells>;
 
 // One logical workgroup `lb` (4 waves) of the step of one solve `a`.
 template <typename T, bool kFrozen, bool kReduce, bool kMulti, int kAT, bool kRowTail = true>
@@ -340,8 +346,9 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
         // <10> faces: east face of row q and north face (q+1/2)
         const int q = r - 2;
         T aq = c.D - c.D * fS, aq1 = c.D - c.D * fC;
-        T fE = (aq + from_right(aq)) * (from_right(uS) - uS);
-        T fN = (aq + aq1) * (uC - uS);
+        const T kE = aq + from_right(aq), kN = aq + aq1;
+        const T gE = from_right(uS) - uS, gN = uC - uS;
+        T fE = kE * gE, fN = kN * gN;
         T dE = pSE - pS, dN = pC - pS;
         T fEA = (aAS + from_right(aAS)) * dE;
         T fNA = (aAS + aAC) * dN;
@@ -357,8 +364,8 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
           fE += c.h * fEA;
           fN += c.h * fNA;
         } else {
-          fE += fEA;
-          fN += fNA;
+          fE = fEA + kE * gE;
+          fN = fNA + kN * gN;
         }
         if constexpr (P >= 4) {
           T div = c.cT * (fE - from_left(fE) + fN - cN);
@@ -375,9 +382,10 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
         T PD = (aq + aE + aq1 + aNE) * T(0.25);
         T PDW = from_left(PD);
         T uE = from_right(uS), uNE = from_right(uC), uNW = from_left(uC);
-        T fE = (aq + aE + PD + cPD) * (uE - uS);
-        T fN = (aq + aq1 + PD + PDW) * (uC - uS);
-        T d1 = PD * (uNE - uS), d2 = PDW * (uNW - uS);
+        const T kE = aq + aE + PD + cPD, kN = aq + aq1 + PD + PDW;
+        const T gE = uE - uS, gN = uC - uS, gNE = uNE - uS, gNW = uNW - uS;
+        T fE = kE * gE, fN = kN * gN;
+        T d1 = PD * gNE, d2 = PDW * gNW;
 
         T PA = T(0);
         if constexpr (!kDiff) {
@@ -435,10 +443,12 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs<T> &a, const int lb
             d1 += c.h * d1A;
             d2 += c.h * d2A;
           } else {
-            fE += fEA;
-            fN += fNA;
-            d1 += d1A;
-            d2 += d2A;
+            // one expression per link, so each U product fuses with the
+            // psi link into a multiply-add
+            fE = fEA + kE * gE;
+            fN = fNA + kN * gN;
+            d1 = d1A + PD * gNE;
+            d2 = d2A + PDW * gNW;
           }
         }
 
@@ -538,7 +548,7 @@ void step2d_kernel(Step2DArgs<T> a) {
 // n0 + k: buffers and frame records are picked from the epoch's parities.
 template <typename T, bool kFrozen, bool kReduce, bool kMulti>
 __global__ __launch_bounds__(256)
-    __attribute__((amdgpu_waves_per_eu(kMinWaves2D<T, kMulti, kAtApproxShells>)))
+    __attribute__((amdgpu_waves_per_eu(kMinWavesBatch2D<T, kMulti>)))
 void batch2d_kernel(const BatchSolve2D<T> *table,
                                                       const int2 *map, int k) {
   const int2 bm = map[blockIdx.x];
