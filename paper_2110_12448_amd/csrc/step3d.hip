@@ -198,6 +198,8 @@ __device__ __forceinline__ bool step3d_tile(const Step3DArgs<T> &a, int strip, i
     return (size_t)j * (size_t)nx;
   };
   auto slot5 = [](int r) { return (r + 10) % 5; };
+  // slot of the row k rows below the row in slot s
+  auto back = [](int s, int k) { return s >= k ? s - k : s + 5 - k; };
   // LDS index of field f at row slot s in z layer zi + dz, this lane's column:
   // the lane's part of the index is computed once (thin tiles have a z row
   // per lane group)
@@ -251,6 +253,9 @@ __device__ __forceinline__ bool step3d_tile(const Step3DArgs<T> &a, int strip, i
 
   T nxt_p, nxt_u, nxt_h = 0;
   int nxt_g = 0;
+  // slot of the row the next iteration publishes, advanced by one per
+  // iteration (the slots of the rows below follow from it without a division)
+  int sr = slot5(y0 - 2);
   {
     size_t ro = rowoff(y0 - 2);
     nxt_p = a.psi_in[pz + ro];
@@ -285,23 +290,42 @@ __device__ __forceinline__ bool step3d_tile(const Step3DArgs<T> &a, int strip, i
       if (ring) nxt_h = a.psi_in[pzh + ro];
       if (kMulti) nxt_g = a.grain[pz + ro];
     }
-    fN = M::tanh_(pN * isq2);
-    const int sN = slot5(r);
-    {
-      const int o = at(kPsi, sN, 0);
-      sm[o] = pN;
-      sm[o + (kU - kPsi) * RS] = uN;
-      sm[o + (kAD - kPsi) * RS] = c.D * (T(1) - fN);
-      if (kMulti) gL[sN * NZR * RS + gzo] = (int8_t)gN;
-      if (ring) sm[sN * SLOTF + zih * LAY + lx + 1] = hN;
+    const int sN = sr;
+    sr = sN == 4 ? 0 : sN + 1;
+    const int oN = at(kPsi, sN, 0);
+    // phi and alpha_D of row r are first read by the links of the next
+    // iteration: phi is formed after the psi phase's first LDS reads are
+    // issued, while they are in flight, and alpha_D stored after them (the
+    // empty asm statements hold that order against the compiler's hoisting
+    // and sinking).  With <111> links the psi phase holds more reads in
+    // flight and ran slower so; there both are formed here.
+    constexpr bool kLatePhi = !kShell3;
+    auto form_fN = [&]() {
+      T pNb = pN;
+      if constexpr (kLatePhi) asm volatile("" : "+v"(pNb));
+      fN = M::tanh_(pNb * isq2);
+      if constexpr (kLatePhi) asm volatile("" : "+v"(fN));
+    };
+    auto publish_aD = [&]() { sm[oN + (kAD - kPsi) * RS] = c.D * (T(1) - fN); };
+    sm[oN] = pN;
+    sm[oN + (kU - kPsi) * RS] = uN;
+    if (kMulti) gL[sN * NZR * RS + gzo] = (int8_t)gN;
+    if (ring) sm[sN * SLOTF + zih * LAY + lx + 1] = hN;
+    if constexpr (!kLatePhi) {
+      form_fN();
+      publish_aD();
     }
     __syncthreads();
     if constexpr (P == 0) {
+      if constexpr (kLatePhi) {
+        form_fN();
+        publish_aD();
+      }
       __syncthreads();
       return;
     }
     const int m = r - 1;
-    const int sm1 = slot5(m - 1), s0 = slot5(m), sp1 = slot5(m + 1);
+    const int sm1 = back(sN, 2), s0 = back(sN, 1), sp1 = sN;
 
     if constexpr (P == 1) {
       // only the y face between rows m and m+1 (lower cell (x, m, z)), in
@@ -312,6 +336,10 @@ __device__ __forceinline__ bool step3d_tile(const Step3DArgs<T> &a, int strip, i
       const T cz1 = L(kPsi, sp1, 1, 0) - L(kPsi, sp1, -1, 0);
       FyS = aniso3<T, 1>(cx0 + cx1, T(4) * (L(kPsi, sp1, 0, 0) - L(kPsi, s0, 0, 0)), cz0 + cz1,
                          rot_of(gC), c, c.f3_eps);
+      if constexpr (kLatePhi) {
+        form_fN();
+        publish_aD();
+      }
       __syncthreads();
       return;
     } else {
@@ -327,6 +355,7 @@ __device__ __forceinline__ bool step3d_tile(const Step3DArgs<T> &a, int strip, i
             if (!kShell3 && dx != 0 && dy != 0 && dz != 0) continue;  // corners unused
             Pn[nb(dx, dy, dz)] = L(kPsi, sy[dy + 1], dz, dx);
           }
+      if constexpr (kLatePhi) form_fN();
       const T p0 = Pn[nb(0, 0, 0)];
       T s1 = T(0), s2 = T(0), s3 = T(0);
       T g1 = T(0), g2 = T(0), g3 = T(0);
@@ -407,6 +436,7 @@ __device__ __forceinline__ bool step3d_tile(const Step3DArgs<T> &a, int strip, i
         aA = (x == -1) ? fr : ((x == nx) ? fl : aA);
       }
       sm[at(kAA, s0, 0)] = aA;
+      if constexpr (kLatePhi) publish_aD();
       aAq = aAm;
       aAm = aA;
       // dynamic grains: the grain of row m at the next level (a liquid cell,
@@ -452,7 +482,16 @@ __device__ __forceinline__ bool step3d_tile(const Step3DArgs<T> &a, int strip, i
       // ---------------- phase C: the links this wave owns at row q = m - 1
       // (P == 3: only those towards row q+1, which the first U row needs)
       const int q = m - 1;
-      const int sl[3] = {yslot(q - 1), yslot(q), yslot(q + 1)};
+      int sl[3];
+      if (a.bcy != PF_BC_NOFLUX || (q >= 1 && q <= ny - 2)) {
+        sl[0] = back(sN, 3);  // rows q-1, q, q+1 = r-3, r-2, r-1
+        sl[1] = back(sN, 2);
+        sl[2] = back(sN, 1);
+      } else {
+        sl[0] = yslot(q - 1);
+        sl[1] = yslot(q);
+        sl[2] = yslot(q + 1);
+      }
       auto rd = [&](int f, int dy, int dz, int dx) -> T {
         return sm[sl[dy + 1] * SLOTF + f * RS + zlo[dz + 1] + dx];
       };
