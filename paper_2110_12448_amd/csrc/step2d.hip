@@ -105,7 +105,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 
 // Waves per SIMD the register budget must leave room for.  The steady-state
 // row group is one basic block, so the scheduler overlaps rows freely: FP32
-// variants settle at 85-131 VGPRs (3-5 waves per SIMD) and run fastest
+// variants settle at 85-132 VGPRs (3-5 waves per SIMD) and run fastest
 // unconstrained; the FP64 approximated-current single-grain variants would
 // take 200+ VGPRs (2 waves) and run 6-18% faster held to 3 waves (168 VGPRs,
 // no spills).  The other FP64 variants would spill there and stay
