@@ -297,8 +297,8 @@ __device__ __forceinline__ bool step3d_tile(const Step3DArgs<T> &a, int strip, i
     // iteration: phi is formed after the psi phase's first LDS reads are
     // issued, while they are in flight, and alpha_D stored after them (the
     // empty asm statements hold that order against the compiler's hoisting
-    // and sinking).  With <111> links the psi phase holds more reads in
-    // flight and ran slower so; there both are formed here.
+    // and sinking).  With <111> links (more reads in flight) that order ran
+    // slower, so there both are formed here, before the barrier.
     constexpr bool kLatePhi = !kShell3;
     auto form_fN = [&]() {
       T pNb = pN;
