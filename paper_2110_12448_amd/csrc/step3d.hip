@@ -476,13 +476,13 @@ __device__ __forceinline__ bool step3d_tile(const Step3DArgs<T> &a, int strip, i
           over = over | (out_lane & (m >= a.shift_row) & (m <= ny - 2) & (fC >= T(0)) & (fN < T(0)));
       }
     }
-    __syncthreads();
-
+    // ---------------- phase C's operands that this iteration's alpha_A does
+    // not feed (psi, U and alpha_D of rows q-1 .. q+1, q = m - 1, all
+    // published before the first barrier): read before the last barrier, so
+    // that after it only the alpha_A reads are waited on
+    const int q = m - 1;
+    int sl[3] = {0, 0, 0};
     if constexpr (P >= 3) {
-      // ---------------- phase C: the links this wave owns at row q = m - 1
-      // (P == 3: only those towards row q+1, which the first U row needs)
-      const int q = m - 1;
-      int sl[3];
       if (a.bcy != PF_BC_NOFLUX || (q >= 1 && q <= ny - 2)) {
         sl[0] = back(sN, 3);  // rows q-1, q, q+1 = r-3, r-2, r-1
         sl[1] = back(sN, 2);
@@ -492,89 +492,99 @@ __device__ __forceinline__ bool step3d_tile(const Step3DArgs<T> &a, int strip, i
         sl[1] = yslot(q);
         sl[2] = yslot(q + 1);
       }
-      auto rd = [&](int f, int dy, int dz, int dx) -> T {
-        return sm[sl[dy + 1] * SLOTF + f * RS + zlo[dz + 1] + dx];
-      };
-      constexpr bool kFull = P == 4;
-      auto abars = [&](int AL, T Pyq) -> Abar9<T> {
-        Abar9<T> o;
-        const T a00 = rd(AL, 0, 0, 0), a10 = rd(AL, 1, 0, 0);
-        const T a0m = rd(AL, 0, -1, 0), a0p = rd(AL, 0, 1, 0);
-        const T a1m = rd(AL, 1, -1, 0), a1p = rd(AL, 1, 1, 0);
-        o.Py1 = c.k1a * a10 + c.k1b * (rd(AL, 1, 0, -1) + rd(AL, 1, 0, 1) + a1m + a1p);
-        o.N = Pyq + o.Py1;
-        // xy plaquettes {x, x+1} x {q, q+1} at z-1, z, z+1
-        const T cm = a0m + a1m, c0 = a00 + a10, cp = a0p + a1p;
-        const T Xm = cm + from_right(cm), X0 = c0 + from_right(c0), Xp = cp + from_right(cp);
-        o.NE = c.k2a * X0 + c.k2b * (Xm + Xp);
-        o.NW = from_left(o.NE);
-        // yz plaquettes {q, q+1} x {z, z+1} (NU) and {z-1, z} (ND) at x-1, x, x+1
-        const T S = c0 + cp, Sd = cm + c0;
-        o.NU = c.k2a * S + c.k2b * (from_left(S) + from_right(S));
-        o.ND = c.k2a * Sd + c.k2b * (from_left(Sd) + from_right(Sd));
-        if constexpr (kShell3) {
-          // the cube {x, x+1} x {q, q+1} x {z, z+1} is two stacked plaquettes
-          o.Tpp = c.k3 * (X0 + Xp);
-          o.Tpm = c.k3 * (X0 + Xm);
-          o.Tmp = from_left(o.Tpp);
-          o.Tmm = from_left(o.Tpm);
-        } else {
-          o.Tpp = o.Tpm = o.Tmp = o.Tmm = T(0);
-        }
-        if constexpr (kFull) {
-          const T am0 = rd(AL, -1, 0, 0), am1 = rd(AL, -1, 1, 0);
-          const T Px = c.k1a * a00 + c.k1b * (am0 + a10 + a0m + a0p);
-          o.E = Px + from_right(Px);
-          const T Pz0 = c.k1a * a00 + c.k1b * (rd(AL, 0, 0, -1) + rd(AL, 0, 0, 1) + am0 + a10);
-          const T Pz1 = c.k1a * a0p + c.k1b * (rd(AL, 0, 1, -1) + rd(AL, 0, 1, 1) + am1 + a1p);
-          o.Up = Pz0 + Pz1;
-          // xz plaquettes {x, x+1} x {z, z+1} at q-1, q, q+1
-          const T ym = am0 + am1, y0s = a00 + a0p, yp = a10 + a1p;
-          const T Ym = ym + from_right(ym), Y0 = y0s + from_right(y0s), Yp = yp + from_right(yp);
-          o.EU = c.k2a * Y0 + c.k2b * (Ym + Yp);
-          o.WU = from_left(o.EU);
-        } else {
-          o.E = o.Up = o.EU = o.WU = T(0);
-        }
-        return o;
-      };
-      auto diffs = [&](int BL) -> Diff9<T> {
-        Diff9<T> o;
-        const T b0 = rd(BL, 0, 0, 0);
-        o.N = rd(BL, 1, 0, 0) - b0;
-        o.NE = rd(BL, 1, 0, 1) - b0;
-        o.NW = rd(BL, 1, 0, -1) - b0;
-        o.NU = rd(BL, 1, 1, 0) - b0;
-        o.ND = rd(BL, 1, -1, 0) - b0;
-        if constexpr (kShell3) {
-          o.Tpp = rd(BL, 1, 1, 1) - b0;
-          o.Tmp = rd(BL, 1, 1, -1) - b0;
-          o.Tpm = rd(BL, 1, -1, 1) - b0;
-          o.Tmm = rd(BL, 1, -1, -1) - b0;
-        } else {
-          o.Tpp = o.Tmp = o.Tpm = o.Tmm = T(0);
-        }
-        if constexpr (kFull) {
-          o.E = rd(BL, 0, 0, 1) - b0;
-          o.Up = rd(BL, 0, 1, 0) - b0;
-          o.EU = rd(BL, 0, 1, 1) - b0;
-          o.WU = rd(BL, 0, 1, -1) - b0;
-        } else {
-          o.E = o.Up = o.EU = o.WU = T(0);
-        }
-        return o;
-      };
-      // P_y of row q itself: carried from the row below except at the start
-      auto py_here = [&](int AL) -> T {
-        return c.k1a * rd(AL, 0, 0, 0) +
-               c.k1b * (rd(AL, 0, 0, -1) + rd(AL, 0, 0, 1) + rd(AL, 0, -1, 0) + rd(AL, 0, 1, 0));
-      };
-      if constexpr (!kFull) {
-        PyD = py_here(kAD);
-        PyA = py_here(kAA);
+    }
+    auto rd = [&](int f, int dy, int dz, int dx) -> T {
+      return sm[sl[dy + 1] * SLOTF + f * RS + zlo[dz + 1] + dx];
+    };
+    constexpr bool kFull = P == 4;
+    auto abars = [&](int AL, T Pyq) -> Abar9<T> {
+      Abar9<T> o;
+      const T a00 = rd(AL, 0, 0, 0), a10 = rd(AL, 1, 0, 0);
+      const T a0m = rd(AL, 0, -1, 0), a0p = rd(AL, 0, 1, 0);
+      const T a1m = rd(AL, 1, -1, 0), a1p = rd(AL, 1, 1, 0);
+      o.Py1 = c.k1a * a10 + c.k1b * (rd(AL, 1, 0, -1) + rd(AL, 1, 0, 1) + a1m + a1p);
+      o.N = Pyq + o.Py1;
+      // xy plaquettes {x, x+1} x {q, q+1} at z-1, z, z+1
+      const T cm = a0m + a1m, c0 = a00 + a10, cp = a0p + a1p;
+      const T Xm = cm + from_right(cm), X0 = c0 + from_right(c0), Xp = cp + from_right(cp);
+      o.NE = c.k2a * X0 + c.k2b * (Xm + Xp);
+      o.NW = from_left(o.NE);
+      // yz plaquettes {q, q+1} x {z, z+1} (NU) and {z-1, z} (ND) at x-1, x, x+1
+      const T S = c0 + cp, Sd = cm + c0;
+      o.NU = c.k2a * S + c.k2b * (from_left(S) + from_right(S));
+      o.ND = c.k2a * Sd + c.k2b * (from_left(Sd) + from_right(Sd));
+      if constexpr (kShell3) {
+        // the cube {x, x+1} x {q, q+1} x {z, z+1} is two stacked plaquettes
+        o.Tpp = c.k3 * (X0 + Xp);
+        o.Tpm = c.k3 * (X0 + Xm);
+        o.Tmp = from_left(o.Tpp);
+        o.Tmm = from_left(o.Tpm);
+      } else {
+        o.Tpp = o.Tpm = o.Tmp = o.Tmm = T(0);
       }
-      const Abar9<T> bD = abars(kAD, PyD), bA = abars(kAA, PyA);
-      const Diff9<T> dU = diffs(kU), dP = diffs(kPsi);
+      if constexpr (kFull) {
+        const T am0 = rd(AL, -1, 0, 0), am1 = rd(AL, -1, 1, 0);
+        const T Px = c.k1a * a00 + c.k1b * (am0 + a10 + a0m + a0p);
+        o.E = Px + from_right(Px);
+        const T Pz0 = c.k1a * a00 + c.k1b * (rd(AL, 0, 0, -1) + rd(AL, 0, 0, 1) + am0 + a10);
+        const T Pz1 = c.k1a * a0p + c.k1b * (rd(AL, 0, 1, -1) + rd(AL, 0, 1, 1) + am1 + a1p);
+        o.Up = Pz0 + Pz1;
+        // xz plaquettes {x, x+1} x {z, z+1} at q-1, q, q+1
+        const T ym = am0 + am1, y0s = a00 + a0p, yp = a10 + a1p;
+        const T Ym = ym + from_right(ym), Y0 = y0s + from_right(y0s), Yp = yp + from_right(yp);
+        o.EU = c.k2a * Y0 + c.k2b * (Ym + Yp);
+        o.WU = from_left(o.EU);
+      } else {
+        o.E = o.Up = o.EU = o.WU = T(0);
+      }
+      return o;
+    };
+    auto diffs = [&](int BL) -> Diff9<T> {
+      Diff9<T> o;
+      const T b0 = rd(BL, 0, 0, 0);
+      o.N = rd(BL, 1, 0, 0) - b0;
+      o.NE = rd(BL, 1, 0, 1) - b0;
+      o.NW = rd(BL, 1, 0, -1) - b0;
+      o.NU = rd(BL, 1, 1, 0) - b0;
+      o.ND = rd(BL, 1, -1, 0) - b0;
+      if constexpr (kShell3) {
+        o.Tpp = rd(BL, 1, 1, 1) - b0;
+        o.Tmp = rd(BL, 1, 1, -1) - b0;
+        o.Tpm = rd(BL, 1, -1, 1) - b0;
+        o.Tmm = rd(BL, 1, -1, -1) - b0;
+      } else {
+        o.Tpp = o.Tmp = o.Tpm = o.Tmm = T(0);
+      }
+      if constexpr (kFull) {
+        o.E = rd(BL, 0, 0, 1) - b0;
+        o.Up = rd(BL, 0, 1, 0) - b0;
+        o.EU = rd(BL, 0, 1, 1) - b0;
+        o.WU = rd(BL, 0, 1, -1) - b0;
+      } else {
+        o.E = o.Up = o.EU = o.WU = T(0);
+      }
+      return o;
+    };
+    // P_y of row q itself: carried from the row below except at the start
+    auto py_here = [&](int AL) -> T {
+      return c.k1a * rd(AL, 0, 0, 0) +
+             c.k1b * (rd(AL, 0, 0, -1) + rd(AL, 0, 0, 1) + rd(AL, 0, -1, 0) + rd(AL, 0, 1, 0));
+    };
+    Diff9<T> dU{}, dP{};
+    Abar9<T> bD{};
+    if constexpr (P >= 3) {
+      dU = diffs(kU);
+      dP = diffs(kPsi);
+      if constexpr (!kFull) PyD = py_here(kAD);
+      bD = abars(kAD, PyD);
+    }
+    __syncthreads();
+
+    if constexpr (P >= 3) {
+      // ---------------- phase C: the links this wave owns at row q
+      // (P == 3: only those towards row q+1, which the first U row needs)
+      if constexpr (!kFull) PyA = py_here(kAA);
+      const Abar9<T> bA = abars(kAA, PyA);
       PyD = bD.Py1;
       PyA = bA.Py1;
       // link values: D~ abar_D dU + abar_A dpsi (D~ is inside alpha_D)
