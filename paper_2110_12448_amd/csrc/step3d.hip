@@ -315,6 +315,25 @@ __device__ __forceinline__ bool step3d_tile(const Step3DArgs<T> &a, int strip, i
       form_fN();
       publish_aD();
     }
+    // The psi phase's neighbourhood of rows r-2 and r-1 was published in
+    // earlier iterations.  With <111> links (18 of its 27 points) it is read
+    // before the barrier, whose wait then covers those reads, and only row r
+    // after it; the 7-point-per-row variants ran about 1% slower so and read
+    // all three rows after the barrier.
+    constexpr bool kEarlyPsi = kShell3;
+    T Pn[27];
+    if constexpr (P >= 2 && kEarlyPsi) {
+      const int syb[2] = {back(sN, 2), back(sN, 1)};
+#pragma unroll
+      for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 0; ++dy)
+#pragma unroll
+          for (int dx = -1; dx <= 1; ++dx) {
+            if (!kShell3 && dx != 0 && dy != 0 && dz != 0) continue;  // corners unused
+            Pn[nb(dx, dy, dz)] = L(kPsi, syb[dy + 1], dz, dx);
+          }
+    }
     __syncthreads();
     if constexpr (P == 0) {
       if constexpr (kLatePhi) {
@@ -325,7 +344,7 @@ __device__ __forceinline__ bool step3d_tile(const Step3DArgs<T> &a, int strip, i
       return;
     }
     const int m = r - 1;
-    const int sm1 = back(sN, 2), s0 = back(sN, 1), sp1 = sN;
+    const int s0 = back(sN, 1), sp1 = sN;
 
     if constexpr (P == 1) {
       // only the y face between rows m and m+1 (lower cell (x, m, z)), in
@@ -344,12 +363,12 @@ __device__ __forceinline__ bool step3d_tile(const Step3DArgs<T> &a, int strip, i
       return;
     } else {
       // ---------------- phase B: psi rate at row m from the LDS neighbourhood
-      T Pn[27];
-      const int sy[3] = {sm1, s0, sp1};
+      // (rows m-1 and m already read when kEarlyPsi; row m+1 = r)
+      const int sy[3] = {back(sN, 2), s0, sp1};
 #pragma unroll
       for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
-        for (int dy = -1; dy <= 1; ++dy)
+        for (int dy = kEarlyPsi ? 1 : -1; dy <= 1; ++dy)
 #pragma unroll
           for (int dx = -1; dx <= 1; ++dx) {
             if (!kShell3 && dx != 0 && dy != 0 && dz != 0) continue;  // corners unused
