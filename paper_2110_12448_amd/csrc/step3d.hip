@@ -315,19 +315,19 @@ __device__ __forceinline__ bool step3d_tile(const Step3DArgs<T> &a, int strip, i
       form_fN();
       publish_aD();
     }
-    // The psi phase's neighbourhood of rows r-2 and r-1 was published in
-    // earlier iterations.  With <111> links (18 of its 27 points) it is read
-    // before the barrier, whose wait then covers those reads, and only row r
-    // after it; the 7-point-per-row variants ran about 1% slower so and read
-    // all three rows after the barrier.
-    constexpr bool kEarlyPsi = kShell3;
+    // The psi phase's neighbourhood in rows r-2 and r-1 (its rows m-1 and m)
+    // was published in earlier iterations: part of it is read before the
+    // barrier, whose wait then covers those reads.  Row m always; row m-1
+    // too with <111> links (18 of the 27 points).  Without them, reading row
+    // m-1 early as well ran slower than row m alone.
+    constexpr int kEarlyFrom = kShell3 ? -1 : 0;  // rows dy = kEarlyFrom .. 0
     T Pn[27];
-    if constexpr (P >= 2 && kEarlyPsi) {
+    if constexpr (P >= 2) {
       const int syb[2] = {back(sN, 2), back(sN, 1)};
 #pragma unroll
       for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
-        for (int dy = -1; dy <= 0; ++dy)
+        for (int dy = kEarlyFrom; dy <= 0; ++dy)
 #pragma unroll
           for (int dx = -1; dx <= 1; ++dx) {
             if (!kShell3 && dx != 0 && dy != 0 && dz != 0) continue;  // corners unused
@@ -363,14 +363,15 @@ __device__ __forceinline__ bool step3d_tile(const Step3DArgs<T> &a, int strip, i
       return;
     } else {
       // ---------------- phase B: psi rate at row m from the LDS neighbourhood
-      // (rows m-1 and m already read when kEarlyPsi; row m+1 = r)
+      // (the rows not read before the barrier; row m+1 = r)
       const int sy[3] = {back(sN, 2), s0, sp1};
 #pragma unroll
       for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
-        for (int dy = kEarlyPsi ? 1 : -1; dy <= 1; ++dy)
+        for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
           for (int dx = -1; dx <= 1; ++dx) {
+            if (dy >= kEarlyFrom && dy <= 0) continue;  // read before the barrier
             if (!kShell3 && dx != 0 && dy != 0 && dz != 0) continue;  // corners unused
             Pn[nb(dx, dy, dz)] = L(kPsi, sy[dy + 1], dz, dx);
           }
