@@ -499,7 +499,9 @@ __device__ __forceinline__ bool step3d_tile(const Step3DArgs<T> &a, int strip, i
     // ---------------- phase C's operands that this iteration's alpha_A does
     // not feed (psi, U and alpha_D of rows q-1 .. q+1, q = m - 1, all
     // published before the first barrier): read before the last barrier, so
-    // that after it only the alpha_A reads are waited on
+    // that after it only the alpha_A reads are waited on.  (At P == 3, whose
+    // q = y0 - 1 can lie below a no-flux wall with row q-1's image at row r,
+    // nothing of row q-1 is read.)
     const int q = m - 1;
     int sl[3] = {0, 0, 0};
     if constexpr (P >= 3) {
