@@ -93,6 +93,11 @@ EDGE3 = [
     ((30, 18, 10), (0, 0, 0), "frozen", (2.0 / 3.0, 0.0, 1.0 / 3.0), 2, (5, 3)),
     # 16-wave workgroups with a ragged last z tile (14 + 3 rows)
     ((50, 22, 17), (1, 0, 0), "frozen", wl.ISO_3D, 2, (8, 14)),
+    # no-flux walls in every direction with 4-row segments, with and without
+    # <111> links: the first link row of the bottom segment lies below the
+    # y wall, and every segment start reads rows of the one below
+    ((24, 21, 12), (0, 0, 0), "frozen", wl.ISO_3D_441, 2, (4, 3)),
+    ((26, 19, 13), (0, 0, 0), "frozen", wl.ISO_3D, 3, (4, 5)),
 ]
 
 
